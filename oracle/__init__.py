@@ -1,0 +1,204 @@
+"""CPU oracle for the MesonGS++ quantization sweep -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  The product library never does.  It shares no
+code with the HIP path; the two meet only through the seeded inputs of
+``paper_2604_26799_amd.synth``.
+
+Everything here is the plain definition written out (C in ``mgs_oracle.c``,
+FP64 accumulation, literal FP32 quantizer), wrapped with NumPy arrays.
+Error codes: 0 ok, -1 invalid argument, -2 non-finite input, -3 infeasible.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+OK, EINVAL, ENONFINITE, EINFEASIBLE = 0, -1, -2, -3
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: oracle status {code}")
+        self.code = code
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "libmgs_oracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        _LIB = ct.CDLL(path)
+        P = ct.c_void_p
+        i64, i32 = ct.c_int64, ct.c_int32
+        _LIB.orc_prune_select.argtypes = [P, i64, P, i32, P]
+        _LIB.orc_quant_sweep.argtypes = [P, i64, i32, i64, P, P, P, i32, i32, P, i32, P, P, P, P, P]
+        _LIB.orc_quantize.argtypes = [P, i64, i32, i64, P, i64, i32, P, P, P, P]
+        _LIB.orc_dequantize.argtypes = [P, i64, i32, i32, P, P, P, P]
+        _LIB.orc_vq_assign.argtypes = [P, i64, i32, P, i32, P, P]
+        _LIB.orc_ilp_exhaustive.argtypes = [P, P, i64, i32, i64, P, P, P]
+        _LIB.orc_ilp_dp.argtypes = [P, P, i64, i32, i64, P, P, P]
+        _LIB.orc_hist_bins.argtypes = [P, i32]
+        _LIB.orc_hist_bins.restype = i64
+        for f in ("orc_prune_select", "orc_quant_sweep", "orc_quantize", "orc_dequantize",
+                  "orc_vq_assign", "orc_ilp_exhaustive", "orc_ilp_dp"):
+            getattr(_LIB, f).restype = ct.c_int
+    return _LIB
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+def _check(code: int, what: str, allow=(OK,)):
+    if code not in allow:
+        raise OracleError(code, what)
+    return code
+
+
+def prune_select(imp: np.ndarray, k) -> np.ndarray:
+    """Kept indices per reserve ratio, concatenated (each ascending)."""
+    imp = np.ascontiguousarray(imp, dtype=np.float32)
+    k = np.ascontiguousarray(k, dtype=np.int64)
+    out = np.empty(int(k.sum()), dtype=np.int32)
+    _check(lib().orc_prune_select(_p(imp), imp.size, _p(k), k.size, _p(out)), "prune_select")
+    return out
+
+
+def gmax_groups(k, G: int) -> int:
+    return int((int(np.max(k)) + G - 1) // G)
+
+
+def quant_sweep(attr: np.ndarray, imp: np.ndarray, kept: np.ndarray, k, G: int, bits,
+                want_hist: bool = False):
+    """Loss / size tables ``err, bits [T][C][Gmax][nb]`` and ``gmin, gmax [T][C][Gmax]``.
+
+    Returns a dict; with ``want_hist`` also ``hist [T][C][Gmax][sum 2^b]``.
+    Raises OracleError on invalid or non-finite input.
+    """
+    attr = np.ascontiguousarray(attr, dtype=np.float32)
+    C, N = attr.shape
+    imp = np.ascontiguousarray(imp, dtype=np.float32)
+    kept = np.ascontiguousarray(kept, dtype=np.int32)
+    k = np.ascontiguousarray(k, dtype=np.int64)
+    bl = np.ascontiguousarray(bits, dtype=np.uint8)
+    T, nb = k.size, bl.size
+    gm = gmax_groups(k, G) if k.size else 0
+    err = np.empty((T, C, gm, nb), dtype=np.float64)
+    bt = np.empty((T, C, gm, nb), dtype=np.float64)
+    mn = np.empty((T, C, gm), dtype=np.float32)
+    mx = np.empty((T, C, gm), dtype=np.float32)
+    hist = None
+    hp = None
+    if want_hist:
+        hb = int(lib().orc_hist_bins(_p(bl), nb))
+        hist = np.empty((T, C, gm, hb), dtype=np.uint32)
+        hp = _p(hist)
+    _check(lib().orc_quant_sweep(_p(attr), N, C, N, _p(imp), _p(kept), _p(k), T, G, _p(bl), nb,
+                                 _p(err), _p(bt), _p(mn), _p(mx), hp), "quant_sweep")
+    return {"err": err, "bits": bt, "gmin": mn, "gmax": mx, "hist": hist}
+
+
+def quantize(attr: np.ndarray, kept: np.ndarray, G: int, bw: np.ndarray):
+    """Codes ``u16[C][k]`` and ``gmin, gmax [C][ceil(k/G)]`` at bit-widths ``bw[C][ng]``."""
+    attr = np.ascontiguousarray(attr, dtype=np.float32)
+    C, N = attr.shape
+    kept = np.ascontiguousarray(kept, dtype=np.int32)
+    k = kept.size
+    ng = (k + G - 1) // G
+    bw = np.ascontiguousarray(bw, dtype=np.uint8).reshape(C, ng)
+    codes = np.empty((C, k), dtype=np.uint16)
+    mn = np.empty((C, ng), dtype=np.float32)
+    mx = np.empty((C, ng), dtype=np.float32)
+    _check(lib().orc_quantize(_p(attr), N, C, N, _p(kept), k, G, _p(bw), _p(codes), _p(mn), _p(mx)),
+           "quantize")
+    return codes, mn, mx
+
+
+def dequantize(codes: np.ndarray, G: int, bw: np.ndarray, gmin: np.ndarray, gmax: np.ndarray):
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    C, k = codes.shape
+    out = np.empty((C, k), dtype=np.float32)
+    _check(lib().orc_dequantize(_p(codes), k, C, G, _p(np.ascontiguousarray(bw, dtype=np.uint8)),
+                                _p(np.ascontiguousarray(gmin, dtype=np.float32)),
+                                _p(np.ascontiguousarray(gmax, dtype=np.float32)), _p(out)),
+           "dequantize")
+    return out
+
+
+def vq_assign(x: np.ndarray, cb: np.ndarray):
+    """``(idx i32[n], dist f64[n])``: nearest codeword, FP64 distances, ties -> lowest index."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    cb = np.ascontiguousarray(cb, dtype=np.float32)
+    n, D = x.shape
+    K = cb.shape[0]
+    idx = np.empty(n, dtype=np.int32)
+    dist = np.empty(n, dtype=np.float64)
+    _check(lib().orc_vq_assign(_p(x), n, D, _p(cb), K, _p(idx), _p(dist)), "vq_assign")
+    return idx, dist
+
+
+def _ilp(fn, err, size, budget):
+    err = np.ascontiguousarray(err, dtype=np.float64)
+    size = np.ascontiguousarray(size, dtype=np.int64)
+    ncls, nopt = err.shape
+    choice = np.empty(ncls, dtype=np.uint8)
+    obj = ct.c_double(0.0)
+    used = ct.c_int64(0)
+    code = fn(_p(err), _p(size), ncls, nopt, int(budget), _p(choice), ct.byref(obj), ct.byref(used))
+    _check(code, "ilp", allow=(OK, EINFEASIBLE))
+    if code == EINFEASIBLE:
+        return None
+    return choice, obj.value, used.value
+
+
+def ilp_exhaustive(err, size, budget):
+    """Exact 0-1 ILP by enumeration (<= 8 classes).  None if infeasible."""
+    return _ilp(lib().orc_ilp_exhaustive, err, size, budget)
+
+
+def ilp_dp(err, size, budget):
+    """Exact 0-1 ILP by dynamic programming over the integer budget.  None if infeasible."""
+    return _ilp(lib().orc_ilp_dp, err, size, budget)
+
+
+METADATA_BITS = 72  # per group: FP32 minimum + FP32 maximum + one byte of bit-width
+
+
+def size_table(bits_table: np.ndarray, n_per_group=None, bit_list=None, mode: str = "entropy"):
+    """Integer ILP sizes per (group, option): ceil(entropy bits) + 72, or n*b + 72."""
+    if mode == "entropy":
+        return np.ceil(bits_table).astype(np.int64) + METADATA_BITS
+    if mode == "linear":
+        n = np.asarray(n_per_group, dtype=np.int64)[:, None]
+        b = np.asarray(bit_list, dtype=np.int64)[None, :]
+        return n * b + METADATA_BITS
+    raise ValueError(mode)
+
+
+def choose_ratio(per_tau):
+    """Reserve-ratio choice of the search, one plain reading of its outer loop.
+
+    ``per_tau``: list of dicts with keys ``tau`` (comparable), ``size8`` (bits of
+    the all-8-bit configuration), ``budget`` (bits), ``obj`` (ILP optimum or None
+    if infeasible).  A ratio whose doubled 8-bit size is below the budget is
+    skipped; among the rest with a feasible ILP the smallest loss wins; a tie
+    goes to the larger ratio.  Returns the index into ``per_tau`` or None.
+    """
+    best = None
+    for i, r in enumerate(per_tau):
+        if 2 * r["size8"] < r["budget"]:
+            continue
+        if r["obj"] is None:
+            continue
+        if best is None or r["obj"] < per_tau[best]["obj"] or (
+                r["obj"] == per_tau[best]["obj"] and r["tau"] > per_tau[best]["tau"]):
+            best = i
+    return best

@@ -1,0 +1,357 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+None of these compare the oracle with itself: the expected values are worked
+by hand from the quantizer and entropy definitions, closed forms, invariants
+that hold for any input, brute force over tiny inputs, or library routines
+(scipy's entropy and MILP solver, Python's sort).
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def one_group(orc, x, b, w=None):
+    """Run one group through every oracle entry point; return codes, xhat, err, bits, hist."""
+    x = np.asarray(x, dtype=np.float32)
+    n = x.size
+    w = np.ones(n, np.float32) if w is None else np.asarray(w, np.float32)
+    attr = x.reshape(1, n)
+    kept = np.arange(n, dtype=np.int32)
+    k = np.array([n], np.int64)
+    sw = orc.quant_sweep(attr, w, kept, k, n, [b], want_hist=True)
+    codes, mn, mx = orc.quantize(attr, kept, n, np.array([[b]], np.uint8))
+    xhat = orc.dequantize(codes, n, np.array([[b]], np.uint8), mn, mx)
+    return codes[0], xhat[0], sw["err"][0, 0, 0, 0], sw["bits"][0, 0, 0, 0], sw["hist"][0, 0, 0]
+
+
+# ---------------------------------------------------------------- quantizer
+def test_hand_cases(orc):
+    cases = json.load(open(os.path.join(HERE, "golden", "quantizer_hand_cases.json")))["cases"]
+    for c in cases:
+        codes, xhat, err, bits, hist = one_group(orc, c["x"], c["b"], c.get("w"))
+        assert codes.tolist() == c["codes"], c
+        assert np.array_equal(xhat, np.asarray(c["xhat"], np.float32)), c
+        assert err == c["err"], c
+        assert bits == pytest.approx(c["bits"], rel=1e-14, abs=1e-14), c
+        assert hist.sum() == len(c["x"])
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 5, 8, 12, 16])
+def test_lattice_closed_form(orc, b):
+    """Values on the quantization lattice {0, S, ..., 2^b S} (for large b a random
+    subset keeping both ends): every element but the top one is reconstructed
+    exactly and the top one is clamped one step down, so err = S^2 exactly."""
+    S = 2.0 ** -3
+    rng = np.random.default_rng(b)
+    if b <= 12:
+        m = np.arange(2 ** b + 1, dtype=np.float64)
+    else:
+        mid = rng.choice(np.arange(1, 2 ** b), 3000, replace=False)
+        m = np.sort(np.concatenate([[0, 2 ** b], mid])).astype(np.float64)
+    x = (m * S).astype(np.float32)
+    codes, xhat, err, bits, hist = one_group(orc, x, b)
+    want = np.minimum(m, 2 ** b - 1).astype(np.uint16)
+    assert np.array_equal(codes, want)
+    assert np.array_equal(xhat[:-1], x[:-1])
+    assert xhat[-1] == np.float32((2 ** b - 1) * S)
+    assert err == S * S
+    n = x.size
+    if b <= 12:  # every code once, the last one twice
+        assert bits == pytest.approx((2 ** b - 1) * math.log2(n) + 2 * math.log2(n / 2), rel=1e-13)
+    else:  # all codes distinct (2^b - 1 drawn or not): n - 1 singletons or n distinct
+        two = (m == 2 ** b - 1).any()
+        want_bits = (n - 2) * math.log2(n) + 2 * math.log2(n / 2) if two else n * math.log2(n)
+        assert bits == pytest.approx(want_bits, rel=1e-13)
+
+
+@pytest.mark.parametrize("b", [1, 4, 9, 16])
+def test_shifted_lattice_negative_zero_point(orc, b):
+    """Lattice shifted to [1, 1 + 2^b S]: Z = round(2^b - max/S) = -1/S exactly, so the
+    codes are unchanged by the shift (a dropped or sign-flipped Z fails this)."""
+    S = 2.0 ** -2
+    m = np.arange(2 ** b + 1, dtype=np.float64) if b < 16 else \
+        np.concatenate([np.arange(0, 2 ** b, 37), [2 ** b]]).astype(np.float64)
+    x = (1.0 + m * S).astype(np.float32)
+    codes, xhat, err, _, _ = one_group(orc, x, b)
+    assert np.array_equal(codes, np.minimum(m, 2 ** b - 1).astype(np.uint16))
+    assert np.array_equal(xhat[:-1], x[:-1])
+    assert err == S * S
+
+
+def test_constant_and_tiny_groups(orc):
+    for x in ([3.5], [-2.0, -2.0], [0.0, -0.0, 0.0]):
+        for b in (1, 7, 16):
+            codes, xhat, err, bits, hist = one_group(orc, x, b)
+            assert (codes == 0).all() and err == 0.0 and bits == 0.0
+            assert (xhat == np.float32(x[0])).all()
+            assert hist[0] == len(x)
+
+
+def random_group(rng, n):
+    kind = rng.integers(0, 4)
+    if kind == 0:
+        x = rng.normal(0, 1, n)
+    elif kind == 1:
+        x = rng.laplace(0, 0.05, n)
+    elif kind == 2:
+        x = rng.normal(-4, 1, n) * 10.0 ** rng.integers(-20, 20)
+    else:
+        x = rng.integers(-5, 5, n) * 0.5 + 100.0
+    return x.astype(np.float32), rng.lognormal(0, 2, n).astype(np.float32)
+
+
+def test_invariants_random_groups(orc):
+    """Codes in range, histogram sums to n, H <= b and H <= log2 n per value,
+    reconstruction within half a step away from the top clamp and 1.5 steps at
+    it, loss nonincreasing in b."""
+    rng = np.random.default_rng(7)
+    bl = list(range(1, 17))
+    for trial in range(60):
+        n = int(rng.integers(1, 700))
+        x, w = random_group(rng, n)
+        attr = x.reshape(1, n)
+        kept = np.arange(n, dtype=np.int32)
+        sw = orc.quant_sweep(attr, w, kept, np.array([n]), n, bl, want_hist=True)
+        err = sw["err"][0, 0, 0]
+        bits = sw["bits"][0, 0, 0]
+        mn, mx = float(sw["gmin"][0, 0, 0]), float(sw["gmax"][0, 0, 0])
+        assert mn == x.min() and mx == x.max()
+        off = 0
+        for i, b in enumerate(bl):
+            h = sw["hist"][0, 0, 0, off:off + 2 ** b]
+            off += 2 ** b
+            assert h.sum() == n
+            assert bits[i] <= b * n * (1 + 1e-12) + 1e-9
+            assert bits[i] <= n * math.log2(n) * (1 + 1e-12) + 1e-9
+            codes, gmn, gmx = orc.quantize(attr, kept, n, np.array([[b]], np.uint8))
+            assert int(codes.max()) <= 2 ** b - 1
+            assert np.array_equal(np.bincount(codes[0], minlength=2 ** b), h)
+            xhat = orc.dequantize(codes, n, np.array([[b]], np.uint8), gmn, gmx)[0]
+            R = np.float32(mx) - np.float32(mn)
+            S = float(R / np.float32(2.0 ** b))
+            if S == 0.0:
+                assert err[i] == 0.0 or mn != mx
+                continue
+            slack = 2.0 ** -21 * (np.abs(x).astype(np.float64) + abs(mn) + abs(mx)) + 1e-300
+            dev = np.abs(xhat.astype(np.float64) - x.astype(np.float64))
+            assert (dev <= 1.5 * S + slack).all()
+            interior = x.astype(np.float64) <= mn + (2 ** b - 2) * S
+            assert (dev[interior] <= 0.5 * S + slack[interior]).all()
+        # the loss never grows with more bits (exact in real arithmetic; tiny slack
+        # for the rounding of t in FP32)
+        for i in range(len(bl) - 1):
+            assert err[i + 1] <= err[i] * (1 + 1e-6) + 1e-300, (trial, bl[i], err[i], err[i + 1])
+
+
+def test_loss_exact_rational(orc):
+    """The FP64 loss equals the exact rational sum of w (xhat - x)^2 over the FP32
+    values to 1e-13 relative."""
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        n = int(rng.integers(2, 200))
+        x, w = random_group(rng, n)
+        for b in (1, 3, 8, 16):
+            codes, xhat, err, _, _ = one_group(orc, x, b, w)
+            exact = sum(Fraction(float(wj)) * (Fraction(float(xh)) - Fraction(float(xj))) ** 2
+                        for wj, xh, xj in zip(w, xhat, x))
+            if exact == 0:
+                assert err == 0.0
+            else:
+                assert abs(Fraction(err) - exact) <= Fraction(1, 10 ** 13) * exact
+
+
+def test_entropy_matches_scipy(orc):
+    """The size table equals n times scipy's base-2 entropy of the code histogram."""
+    from scipy.stats import entropy
+    rng = np.random.default_rng(11)
+    for trial in range(30):
+        n = int(rng.integers(1, 3000))
+        x, w = random_group(rng, n)
+        bl = [1, 2, 5, 9, 16]
+        sw = orc.quant_sweep(x.reshape(1, n), w, np.arange(n, dtype=np.int32), np.array([n]), n, bl,
+                             want_hist=True)
+        off = 0
+        for i, b in enumerate(bl):
+            h = sw["hist"][0, 0, 0, off:off + 2 ** b].astype(np.float64)
+            off += 2 ** b
+            want = n * entropy(h, base=2) if h.sum() > 0 else 0.0
+            assert sw["bits"][0, 0, 0, i] == pytest.approx(want, rel=1e-12, abs=1e-9)
+
+
+def test_uniform_histogram_entropy(orc):
+    """Every code used equally often -> exactly n*b bits."""
+    for b in (1, 2, 4, 8):
+        reps = 3
+        m = np.repeat(np.arange(2 ** b, dtype=np.float64), reps)
+        x = np.append(m, 2 ** b).astype(np.float32)  # top element clamps onto the last code
+        # drop one copy of the last code so every code appears exactly `reps` times
+        x = np.delete(x, np.where(x == 2 ** b - 1)[0][0])
+        _, _, _, bits, hist = one_group(orc, x, b)
+        assert (hist == reps).all()
+        assert bits == pytest.approx(x.size * b, rel=1e-14)
+
+
+def test_groups_and_ratios_layout(orc):
+    """Tables of several ratios / channels / ragged groups equal the one-group
+    results of the same slices (the layout [t][c][g][b] and NaN padding)."""
+    from paper_2604_26799_amd import synth
+    attr, imp = synth.scene(3000, 11, seed=5)
+    k = np.array([700, 3000, 1501], np.int64)
+    kept = orc.prune_select(imp, k)
+    G, bl = 256, [2, 5, 16]
+    sw = orc.quant_sweep(attr, imp, kept, k, G, bl)
+    gm = (3000 + G - 1) // G
+    assert sw["err"].shape == (3, 11, gm, 3)
+    offs = np.concatenate([[0], np.cumsum(k)])
+    for t in range(3):
+        J = kept[offs[t]:offs[t + 1]]
+        ng = (k[t] + G - 1) // G
+        assert np.isnan(sw["err"][t, :, ng:]).all()
+        for c in (0, 3, 10):
+            for g in (0, ng - 1):
+                sl = J[g * G:(g + 1) * G]
+                x = attr[c, sl]
+                for i, b in enumerate(bl):
+                    _, _, e, s, _ = one_group(orc, x, b, imp[sl])
+                    assert sw["err"][t, c, g, i] == e and sw["bits"][t, c, g, i] == s
+
+
+def test_nonfinite_rejected(orc):
+    x = np.array([[0.0, np.inf, 1.0]], np.float32)
+    with pytest.raises(orc.OracleError) as e:
+        orc.quant_sweep(x, np.ones(3, np.float32), np.arange(3, dtype=np.int32), np.array([3]), 3, [4])
+    assert e.value.code == orc.ENONFINITE
+
+
+# ---------------------------------------------------------------- pruning
+def test_prune_hand_ties(orc):
+    imp = np.array([1, 3, 3, 2, 3], np.float32)
+    kept = orc.prune_select(imp, [2, 3, 4, 0, 5])
+    assert kept.tolist() == [1, 2] + [1, 2, 4] + [1, 2, 3, 4] + [] + [0, 1, 2, 3, 4]
+
+
+def test_prune_vs_sorted(orc):
+    rng = np.random.default_rng(0)
+    for trial in range(20):
+        n = int(rng.integers(1, 3000))
+        imp = rng.lognormal(0, 2, n).astype(np.float32)
+        if trial % 2:  # heavy ties
+            imp = np.round(imp, 1).astype(np.float32)
+        imp[rng.integers(0, n, n // 10)] = 0.0
+        k = np.sort(rng.integers(0, n + 1, 5)).astype(np.int64)
+        kept = orc.prune_select(imp, k)
+        order = sorted(range(n), key=lambda i: (-float(imp[i]), i))
+        off = 0
+        prev = set()
+        for kt in k:
+            want = sorted(order[:kt])
+            got = kept[off:off + kt].tolist()
+            off += kt
+            assert got == want
+            assert prev <= set(got)
+            prev = set(got)
+
+
+# ---------------------------------------------------------------- VQ
+def test_vq_brute_force(orc):
+    rng = np.random.default_rng(1)
+    for n, D, K in [(500, 36, 64), (300, 1, 7), (200, 5, 1), (400, 36, 300)]:
+        x = rng.laplace(0, 0.03, (n, D)).astype(np.float32)
+        cb = x[rng.choice(n, K, replace=False)] if K <= n else rng.normal(0, 1, (K, D)).astype(np.float32)
+        idx, dist = orc.vq_assign(x, cb)
+        d = ((x[:, None, :].astype(np.float64) - cb[None, :, :].astype(np.float64)) ** 2).sum(-1)
+        assert np.array_equal(idx, d.argmin(1).astype(np.int32))
+        np.testing.assert_allclose(dist, d.min(1), rtol=1e-12)
+
+
+def test_vq_self_and_duplicates(orc):
+    rng = np.random.default_rng(2)
+    cb = rng.normal(0, 1, (50, 36)).astype(np.float32)
+    cb[30] = cb[10]  # duplicated codeword: the lower index wins
+    idx, dist = orc.vq_assign(cb, cb)
+    want = np.arange(50)
+    want[30] = 10
+    assert np.array_equal(idx, want) and (dist == 0).all()
+
+
+# ---------------------------------------------------------------- ILP
+def test_ilp_hand_case(orc):
+    err = np.array([[4.0, 1.0], [3.0, 2.0]])
+    size = np.array([[10, 20], [10, 20]])
+    for solve in (orc.ilp_exhaustive, orc.ilp_dp):
+        choice, obj, used = solve(err, size, 30)
+        assert choice.tolist() == [1, 0] and obj == 4.0 and used == 30
+
+
+def test_ilp_budget_edges(orc):
+    rng = np.random.default_rng(4)
+    err = np.sort(rng.uniform(0, 10, (5, 4)), axis=1)[:, ::-1].copy()
+    size = np.sort(rng.integers(1, 50, (5, 4)), axis=1)
+    for solve in (orc.ilp_exhaustive, orc.ilp_dp):
+        big = solve(err, size, int(size.max(1).sum()) + 5)
+        assert big[0].tolist() == list(np.argmin(err, axis=1))
+        tight = solve(err, size, int(size.min(1).sum()))
+        assert (size[np.arange(5), tight[0]] == size.min(1)).all()
+        assert solve(err, size, int(size.min(1).sum()) - 1) is None
+
+
+def test_ilp_exhaustive_vs_dp(orc):
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        ncls = int(rng.integers(1, 6))
+        nopt = int(rng.integers(1, 6))
+        err = rng.uniform(0, 100, (ncls, nopt))
+        size = rng.integers(0, 40, (ncls, nopt))
+        if trial % 3 == 0:
+            err[:, -1] = err[:, 0]  # exact ties across options
+            size[:, -1] = size[:, 0]
+        budget = int(rng.integers(0, 40 * ncls))
+        a = orc.ilp_exhaustive(err, size, budget)
+        b = orc.ilp_dp(err, size, budget)
+        assert (a is None) == (b is None)
+        if a is not None:
+            assert a[1] == pytest.approx(b[1], rel=1e-12) and a[2] == b[2]
+            assert a[0].tolist() == b[0].tolist()
+
+
+def test_ilp_dp_vs_highs(orc):
+    """The DP optimum equals scipy's MILP (HiGHS) optimum on medium tables."""
+    from scipy.optimize import LinearConstraint, milp
+    rng = np.random.default_rng(6)
+    for trial in range(6):
+        ncls, nopt = 30, 8
+        err = np.sort(rng.lognormal(0, 2, (ncls, nopt)), axis=1)[:, ::-1].copy()
+        size = np.sort(rng.integers(5, 400, (ncls, nopt)), axis=1)
+        budget = int(rng.uniform(size.min(1).sum(), size.max(1).sum()))
+        choice, obj, used = orc.ilp_dp(err, size, budget)
+        A_eq = np.kron(np.eye(ncls), np.ones(nopt))
+        cons = [LinearConstraint(A_eq, 1, 1), LinearConstraint(size.reshape(1, -1), 0, budget)]
+        res = milp(err.ravel(), constraints=cons, integrality=np.ones(ncls * nopt),
+                   bounds=(0, 1), options={"mip_rel_gap": 0})
+        assert res.status == 0
+        assert obj == pytest.approx(res.fun, rel=1e-9)
+        assert used <= budget
+
+
+def test_search_space_reading():
+    """The paper's 2.96e722 options for (C, B, Q) = (10, 60, 16) is Q^(C*B):
+    Q options per block, not (C*B)^Q."""
+    assert 600 * math.log10(16) == pytest.approx(722 + math.log10(2.96), abs=2e-3)
+    assert 16 * math.log10(600) < 50
+
+
+def test_choose_ratio_rule(orc):
+    rows = [
+        {"tau": Fraction(1, 10), "size8": 40, "budget": 100, "obj": 1.0},   # skipped: 2*40 < 100
+        {"tau": Fraction(2, 10), "size8": 60, "budget": 100, "obj": 5.0},
+        {"tau": Fraction(3, 10), "size8": 80, "budget": 100, "obj": None},  # infeasible
+        {"tau": Fraction(4, 10), "size8": 90, "budget": 100, "obj": 5.0},   # tie -> larger tau
+        {"tau": Fraction(5, 10), "size8": 99, "budget": 100, "obj": 7.0},
+    ]
+    assert orc.choose_ratio(rows) == 3
