@@ -1,0 +1,198 @@
+/*
+ * mgs.h -- C ABI of libmgs, the MI355X (gfx950) hot path of the MesonGS++
+ * size-aware configuration search (arXiv 2604.26799).
+ *
+ * Conventions for every entry point
+ *   - d_* arguments are device pointers (HIP device memory of the current
+ *     device), h_* arguments are host pointers.
+ *   - The caller owns every buffer.  Entry points that need scratch space
+ *     take a caller-provided device workspace (d_ws, ws_bytes) sized by the
+ *     matching *_ws_bytes() query; nothing is allocated on these calls.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued asynchronously on it; host arguments are read
+ *     before the call returns, so they may be freed right after.
+ *   - Every call returns an int status: MGS_OK (0) or a negative code.
+ *     Argument errors are detected before anything is enqueued.  Errors that
+ *     depend on data (non-finite inputs) are raised on the device into a
+ *     status word kept in the workspace; mgs_status_fetch() synchronises the
+ *     stream and returns it.  Launch failures return MGS_EDEVICE.
+ *   - Layouts are row-major.  The attribute matrix is structure-of-arrays:
+ *     attr[c * ld + i] is channel c of Gaussian i.
+ */
+#ifndef MGS_H
+#define MGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGS_OK 0
+#define MGS_EINVAL (-1)       /* bad argument (NULL, size, range, order) */
+#define MGS_ENONFINITE (-2)   /* an input that must be finite was not */
+#define MGS_EINFEASIBLE (-3)  /* 0-1 ILP: even the smallest allocation exceeds the budget */
+#define MGS_EDEVICE (-4)      /* HIP launch or runtime failure */
+#define MGS_EWORKSPACE (-5)   /* workspace missing or smaller than the query says */
+#define MGS_ELIMIT (-6)       /* 0-1 ILP: exact search exceeded its state limit */
+
+/* Largest limits of the entry points. */
+#define MGS_MAX_RATIOS 64     /* reserve ratios per sweep */
+#define MGS_MAX_GROUP 65535   /* group size G (histogram counts are 16-bit) */
+#define MGS_MAX_BITS 16       /* candidate bit-widths are in [1, 16] */
+#define MGS_MAX_VQ_DIM 64     /* vector length of VQ assignment */
+
+/* Text for a status code (static storage). */
+const char* mgs_strerror(int status);
+
+/* Library version string (static storage). */
+const char* mgs_version(void);
+
+/*
+ * Status word of a workspace: synchronises `stream`, returns MGS_ENONFINITE if
+ * the last call that used d_ws met a non-finite value, MGS_OK otherwise.
+ */
+int mgs_status_fetch(const void* d_ws, void* stream);
+
+/* ======================================================================
+ * Reserve-ratio pruning (paper: section "Gaussians Pruning"; the reserve
+ * ratio tau keeps the tau*N most important Gaussians and cuts the rest).
+ *
+ * For each of T keep counts h_k[t] (0 <= h_k[t] <= n), select the h_k[t]
+ * Gaussians with the largest importance d_imp; equal importance is broken
+ * by the smaller index (-0 and +0 compare equal).  d_kept receives, for
+ * t = 0..T-1 in turn, the h_k[t] selected indices in ascending order
+ * (int32, total sum_t h_k[t] entries).  Counts need not be sorted.
+ * Errors: MGS_EINVAL (n < 0 or n >= 2^31, T outside [1, MGS_MAX_RATIOS], a
+ * count out of range, NULL pointer with nonzero size), MGS_EWORKSPACE;
+ * non-finite importance raises MGS_ENONFINITE in the status word and
+ * leaves d_kept unspecified.
+ * ====================================================================== */
+size_t mgs_prune_select_ws_bytes(int64_t n, int32_t T);
+int mgs_prune_select(const float* d_imp, int64_t n, const int64_t* h_k, int32_t T,
+                     int32_t* d_kept, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ======================================================================
+ * Group-wise quantization sweep (paper: section "Group-wise Attribute
+ * Quantization" for the quantizer, section "Acceleration" for the loss
+ * table Omega, section "Size Estimator" for the entropy size).
+ *
+ * For each reserve ratio t, channel c and group g -- the kept Gaussians
+ * d_kept[koff_t + g*G .. min((g+1)*G, k_t)) where koff_t = sum_{s<t} k_s --
+ * and each candidate bit-width b = h_bits[i]:
+ *   S = (max - min) / 2^b,  Z = round(2^b - max / S)       (FP32, half-even)
+ *   q = round(clamp(x / S + Z, 0, 2^b - 1)),  xhat = (q - Z) * S
+ *   (a group with S == 0 has q = 0 and xhat = min)
+ *   err [t][c][g][i] = sum_j w_j (xhat_j - x_j)^2   with w = d_imp   (FP64)
+ *   bits[t][c][g][i] = sum_k h_k log2(n / h_k) over the code histogram h (FP64)
+ *   gmin/gmax[t][c][g] = group minimum / maximum (FP32)
+ * Tables hold Gmax = ceil(max_t k_t / G) group slots per (t, c); slots past
+ * ceil(k_t / G) are NaN.  d_hist (optional, may be NULL) receives the code
+ * histograms, uint32 [T][C][Gmax][sum_i 2^bits[i]] (2^b bins per listed b,
+ * in list order); meant for small inputs.  Codes and histograms are exact;
+ * err and bits agree with an FP64 evaluation of the definitions to ~1e-12.
+ * Limits: 1 <= G <= MGS_MAX_GROUP, 1 <= T <= MGS_MAX_RATIOS, h_bits strictly
+ * increasing in [1, 16], ld >= N, 0 <= k_t <= N, kept indices in [0, N).
+ * Errors: MGS_EINVAL, MGS_EWORKSPACE; non-finite attributes or weights in a
+ * group, or a group range max - min that overflows, set NaN for that group
+ * and MGS_ENONFINITE in the status word.
+ * ====================================================================== */
+typedef struct {
+    int64_t N;              /* Gaussians in the scene */
+    int64_t ld;             /* row stride of d_attr, in elements (>= N) */
+    int32_t C;              /* attribute channels */
+    int32_t T;              /* reserve ratios */
+    int32_t G;              /* group size */
+    int32_t nb;             /* number of candidate bit-widths */
+    const int64_t* h_k;     /* host [T]: kept Gaussians per ratio */
+    const uint8_t* h_bits;  /* host [nb]: candidate bit-widths */
+} mgs_sweep_desc;
+
+size_t mgs_quant_sweep_ws_bytes(const mgs_sweep_desc* desc);
+int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                    const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                    float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ======================================================================
+ * Final quantization at a chosen bit allocation, and its inverse (paper:
+ * section "Group-wise Attribute Quantization"; the stored metadata are the
+ * per-block minimum and maximum, section "Entropy Encoding").
+ *
+ * mgs_quantize: groups g of G consecutive entries of d_kept (k entries, the
+ * last group may be shorter); ng = ceil(k / G).  For channel c the group
+ * uses b = d_bw[c * ng + g] (1..16).  Writes d_codes[c * k + j] (uint16,
+ * the code q of the sweep's definition) and d_gmin/d_gmax[c * ng + g].
+ * mgs_dequantize: d_out[c * k + j] = xhat = (q - Z) * S, with S and Z
+ * recomputed from the stored minimum, maximum and b (min when S == 0).
+ * Errors: MGS_EINVAL (C < 1, k < 0, G outside [1, MGS_MAX_GROUP], NULL).
+ * Bit-widths outside [1, 16] in d_bw are clamped into range on the device.
+ * ====================================================================== */
+int mgs_quantize(const float* d_attr, int64_t ld, int32_t C, const int32_t* d_kept, int64_t k,
+                 int32_t G, const uint8_t* d_bw, uint16_t* d_codes, float* d_gmin, float* d_gmax,
+                 void* stream);
+int mgs_dequantize(const uint16_t* d_codes, int64_t k, int32_t C, int32_t G, const uint8_t* d_bw,
+                   const float* d_gmin, const float* d_gmax, float* d_out, void* stream);
+
+/* ======================================================================
+ * Nearest-codeword assignment of the vector quantizer for the higher-degree
+ * SH coefficients (paper: section "Attribute Transformation", clustering of
+ * the 1+D SH coefficients with a codebook and an index table).
+ *
+ * d_idx[i] = argmin_j sum_d (x[i][d] - cb[j][d])^2, the distance summed in
+ * FP64 over d in order; ties go to the smallest j.  d_x is [N][D] and d_cb
+ * [K][D], both row-major FP32.  d_dist (optional) receives that FP64
+ * distance of the winner.  d_nfallback (optional, device int64) receives
+ * the number of rows that needed the exact full scan.  Exact: the result
+ * equals the FP64 definition bit for bit.
+ * Limits: 1 <= D <= MGS_MAX_VQ_DIM, 1 <= K < 2^31, N >= 0.
+ * Errors: MGS_EINVAL, MGS_EWORKSPACE; non-finite data -> MGS_ENONFINITE in
+ * the status word.
+ * ====================================================================== */
+size_t mgs_vq_assign_ws_bytes(int64_t N, int32_t D, int32_t K);
+int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float* d_cb, int32_t K,
+                  int32_t* d_idx, double* d_dist, int64_t* d_nfallback, void* d_ws,
+                  size_t ws_bytes, void* stream);
+
+/* ======================================================================
+ * Host side of the search (CPU).
+ *
+ * mgs_ilp_solve: the 0-1 ILP of the bit allocation (paper: equation "ilp"
+ * of section "Solve the MINLP"): one option per class, minimise
+ * sum err[c][x_c] subject to sum size[c][x_c] <= budget.  err is FP64
+ * [ncls][nopt], size int64 [ncls][nopt] (>= 0).  Exact.  Among optimal
+ * solutions the smaller total size wins, then the smaller option index in
+ * class order.  Writes h_choice[ncls] (option index), *h_obj and *h_used.
+ * Returns MGS_EINFEASIBLE when no allocation fits, MGS_EINVAL on bad
+ * arguments (nopt outside [1, 255], non-finite err, negative size),
+ * MGS_ELIMIT if the exact search would need more than 2e7 DP states.
+ *
+ * mgs_size_table: the ILP sizes from a sweep's bits table: size =
+ * ceil(bits) + 72 metadata bits per group (two FP32 bounds and one byte of
+ * bit-width) when mode == 0 (entropy size); n * b + 72 when mode == 1 (the
+ * linear estimator P*Q of equation "size_estim").
+ *
+ * mgs_search: the reserve-ratio loop of the search algorithm over one
+ * sweep's tables (host copies, layout of mgs_quant_sweep): for each ratio t
+ * build the ILP over its C * ceil(k_t / G) groups, skip t when twice the
+ * all-8-bit size is below the budget, solve, and choose the ratio with the
+ * smallest loss (ties: larger t).  Writes h_best_t, the chosen bit-widths
+ * h_best_bits[C][ceil(k_best / G)] (caller sizes it for the largest k),
+ * and per ratio h_obj[t] (NaN when skipped or infeasible) and h_used[t].
+ * Ratios are solved on up to `threads` host threads (0 = all cores).
+ * Returns MGS_EINFEASIBLE when no ratio is admissible.
+ * ====================================================================== */
+int mgs_ilp_solve(const double* h_err, const int64_t* h_size, int64_t ncls, int32_t nopt,
+                  int64_t budget, uint8_t* h_choice, double* h_obj, int64_t* h_used);
+
+int mgs_size_table(const double* h_bits, const int64_t* h_n, int64_t ncls, int32_t nb,
+                   const uint8_t* h_bitlist, int32_t mode, int64_t* h_size);
+
+int mgs_search(const mgs_sweep_desc* desc, const double* h_err, const double* h_bits,
+               int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t* h_best_t,
+               uint8_t* h_best_bits, double* h_obj, int64_t* h_used);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGS_H */

@@ -1,0 +1,97 @@
+// Internal declarations of the quantization sweep (not part of the C ABI).
+#pragma once
+
+#include "common.h"
+
+namespace mgs {
+
+constexpr int LGTAB = 256;            // h * log2(h) table entries kept in LDS
+constexpr int MGS_MAX_ENTRIES = 40;   // histogram windows per plan
+
+// One histogram window of one bit-width inside a batch of LDS words.
+struct HistEntry {
+    int16_t bi;       // index into the bit-width list
+    uint8_t packed;   // two 16-bit bins per 32-bit word
+    uint8_t first;    // first window of this b: it also accumulates the loss
+    uint8_t split;    // the b's bins span more than one window
+    uint8_t pad[3];
+    int32_t lo;       // first word of the window within the b's words
+    int32_t nwords;   // words in the window
+    int32_t lds_off;  // word offset of the window inside the batch
+};
+
+// Everything the kernels need to know about one scene's sweep.
+struct SceneDesc {
+    const float* attr;
+    const float* imp;
+    const int32_t* kept;
+    double* err;
+    double* bits;
+    float* gmin;
+    float* gmax;
+    uint32_t* hist;
+    int64_t ld;
+    int64_t hist_bins;              // sum over the list of 2^b
+    int32_t C, T, G, nb;
+    int32_t gmaxn;                  // group slots per (t, c) in the tables
+    int32_t gpc;                    // real groups per channel, sum_t ceil(k_t / G)
+    int32_t bmax;
+    int32_t pad;
+    int64_t k[MGS_MAX_RATIOS];
+    int64_t koff[MGS_MAX_RATIOS];
+    int32_t gcum[MGS_MAX_RATIOS + 1];  // prefix of ceil(k_t / G) over t
+    int32_t pad2;
+    int64_t hoff[MGS_MAX_BITS];        // debug-histogram offset of each b
+    uint8_t bl[MGS_MAX_BITS];
+};
+
+// A tile of a multi-scene work list.
+struct TileRef {
+    int32_t scene;
+    int32_t t;
+    int32_t c;
+    int32_t g;
+};
+
+// Kernel arguments shared by all tiles of one launch.
+struct SweepParams {
+    mgs_status_block* status;
+    const SceneDesc* scenes;  // device array (workspace)
+    const double* lgtab;      // h * log2(h) for h in [0, lgtab_max] (workspace)
+    int64_t ntiles;
+    int32_t lgtab_max, pad0;
+    int32_t nbatches, nentries, max_batch_words, pad;
+    int32_t batch_begin[MGS_MAX_ENTRIES + 1];
+    int32_t batch_words[MGS_MAX_ENTRIES];
+    HistEntry entries[MGS_MAX_ENTRIES];
+};
+
+// Launch shape and LDS capacity of the sweep kernel.
+struct Shape {
+    int nt;        // threads per workgroup
+    int ept;       // elements per thread (nt * ept >= G)
+    int lds_cap;   // LDS bytes the histogram plan may use (0 = device maximum)
+};
+
+int fill_scene(const mgs_sweep_desc* d, const float* attr, const float* imp, const int32_t* kept,
+               double* err, double* bits, float* gmin, float* gmax, uint32_t* hist, SceneDesc* sc);
+bool build_plan(const uint8_t* bl, int nb, int cap_words, SweepParams* p);
+int plan_for(const SceneDesc& sc, const Shape& sh, SweepParams* p, size_t* lds_bytes);
+Shape default_shape(int G, int nb, int bmax);
+bool shape_valid(const Shape& sh, int G);
+// Copies `count` scene descriptors into device memory and prepares the
+// tables (NaN padding, status reset, debug histogram clearing).
+int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
+                mgs_status_block* status, double* lgtab, int lgtab_max, hipStream_t s);
+int launch_sweep(const SweepParams& p, const TileRef* tiles, const Shape& sh, size_t lds,
+                 int64_t grid, hipStream_t s);
+int max_resident_blocks(const Shape& sh, size_t lds);
+int device_cus();
+int variant_count();
+Shape variant_shape(int i);
+
+// Autotune registry: the shape chosen for (G, nb, bmax), if any.
+bool tuned_shape(int G, int nb, int bmax, Shape* out);
+void set_tuned_shape(int G, int nb, int bmax, const Shape& sh);
+
+}  // namespace mgs

@@ -1,0 +1,717 @@
+// Group-wise quantization sweep: loss and entropy-size tables for every
+// (reserve ratio, channel, group, candidate bit-width).
+//
+// Quantizer (paper, section "Group-wise Attribute Quantization"):
+//   S = (max - min) / 2^b,  Z = round(2^b - max / S),
+//   q = round(clamp(x / S + Z, 0, 2^b - 1)),  xhat = (q - Z) * S.
+// Loss table (section "Acceleration"): importance-weighted sum of squared
+// errors per group and b.  Size table (section "Size Estimator"): Shannon
+// bound n * H of the group's codes, in bits.
+//
+// One workgroup owns one tile (ratio t, channel c, group g).  It gathers the
+// group's values and weights into registers once, reduces min / max, and
+// then evaluates every candidate b from those registers: quantize,
+// dequantize, error, and an LDS histogram of the codes.  Histograms are
+// laid out in LDS per "batch" of bit-widths that fit together; a b whose
+// 2^b bins exceed the LDS capacity is split into bin windows counted in
+// separate passes.  Bins are 32-bit counters, or two 16-bit counters per
+// word where that is needed to fit (counts never exceed G <= 65535).
+//
+// Bit exactness of the codes.  The quantizer is evaluated with single FP32
+// operations, round-half-even, no contraction (built -ffp-contract=off) and
+// IEEE denormals.  Two exact rewrites save work per element and b:
+//   1. x / S_b == (x / R) * 2^b whenever S_b = R * 2^-b is normal for every
+//      listed b: S_b is then an exact power-of-two scaling of R, and
+//      rounding commutes with such scalings while results stay normal;
+//      a subnormal x / R only occurs for values far below the step and
+//      leaves the code unchanged (it is absorbed by Z or rounds to 0).
+//      fl(fl(x/S) + Z) is then one fma(x/R, 2^b, Z).  Groups that fail the
+//      test (R < 2^(bmax - 126)) use the literal division per element.
+//   2. round(clamp(t, 0, 2^b - 1)) == clamp(fl(t + 2^23), 2^23, 2^23 + 2^b - 1)
+//      - 2^23: adding 2^23 rounds any t in [0, 2^23) to an integer
+//      half-even, the clamp bounds are integers and fl() is monotone.  With
+//      |Z| <= 2^23, fl(q - Z) is fl((t' ) - (2^23 + Z)) because both
+//      operands are exact.
+// The loss uses FP64 per term, d = (double)xhat - (double)x exactly, and
+// accumulates in a fixed order (lane, wave, then waves in index order), so
+// results are deterministic and within ~1e-13 of an in-order FP64 sum.
+// The size is n log2 n - sum_k h_k log2 h_k in FP64 (h log2 h from an LDS
+// table for h < 256), which equals sum_k h_k log2(n / h_k) to ~1e-12
+// relative.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <type_traits>
+#include <vector>
+
+#include "common.h"
+#include "sweep.h"
+
+namespace mgs {
+
+// h * log2(h): small h from the LDS copy, larger h from the workspace table
+// (both written from the same FP64 evaluation by the init kernel).
+__device__ __forceinline__ double hlog2h(uint32_t h, const double* lg, const double* lgt) {
+    if (h < 2u) return 0.0;
+    if (h < (uint32_t)LGTAB) return lg[h];
+    return lgt[h];
+}
+
+// FP64 value of a per-element copy.  For FP32 copies an empty asm with a
+// register constraint keeps the compiler from hoisting the conversion out of
+// the bit-width loop (which would double the registers the copy takes).
+template <typename XT>
+__device__ __forceinline__ double as_f64(XT v) {
+    if constexpr (sizeof(XT) == 4) asm volatile("" : "+v"(v));
+    return (double)v;
+}
+
+// One histogram-window pass over the tile's elements for one bit-width on
+// the fast path (x / S_b from x / R, 2^23 rounding trick), specialised on
+// packed bins, ragged group and whether the loss is accumulated here.
+template <int NT, int EPT, typename XT, bool PACKED, bool CHECK, bool ERR>
+__device__ __forceinline__ double eval_fast(const float (&u)[EPT], const XT (&xd)[EPT],
+                                            const XT (&wd)[EPT], int n, int tid, float P,
+                                            float S, float Z, uint32_t* hist, int base) {
+    const float M = 8388608.0f;  // 2^23
+    const float MZ = M + Z;
+    const float hi = M + (P - 1.0f);
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        if (CHECK && i * NT + tid >= n) continue;
+        float t = __builtin_fmaf(u[i], P, Z);
+        float tm = __builtin_amdgcn_fmed3f(t + M, M, hi);
+        uint32_t qi = __float_as_uint(tm) - 0x4B000000u;
+        if (PACKED)
+            atomicAdd(&hist[base + (int)(qi >> 1)], 1u << ((qi & 1u) << 4));
+        else
+            atomicAdd(&hist[base + (int)qi], 1u);
+        if (ERR) {
+            float xh = (tm - MZ) * S;
+            double d = (double)xh - as_f64(xd[i]);
+            acc = __builtin_fma(as_f64(wd[i]), d * d, acc);
+        }
+    }
+    return acc;
+}
+
+// The same pass for the rare cases, with runtime switches: bins split into
+// windows, |Z| > 2^23 (rint path) or the literal division per element.
+template <int NT, int EPT, typename XT>
+__device__ __forceinline__ double eval_generic(const float (&u)[EPT], const XT (&xd)[EPT],
+                                            const XT (&wd)[EPT], int n, int tid, float P,
+                                            float S, float Z, uint32_t* hist, int base, int lo,
+                                            int nwords, bool packed, bool literal, bool err) {
+    const float qmax = P - 1.0f;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        if (i * NT + tid >= n) continue;
+        float t;
+        if (literal) {
+            float x = (float)xd[i];
+            t = x / S;
+            t = t + Z;
+        } else {
+            t = __builtin_fmaf(u[i], P, Z);
+        }
+        t = __builtin_amdgcn_fmed3f(t, 0.0f, qmax);
+        float q = __builtin_rintf(t);
+        uint32_t qi = (uint32_t)q;
+        int word = packed ? (int)(qi >> 1) : (int)qi;
+        uint32_t inc = packed ? (1u << ((qi & 1u) << 4)) : 1u;
+        if ((uint32_t)(word - lo) < (uint32_t)nwords) atomicAdd(&hist[base + word], inc);
+        if (err) {
+            float xh = (q - Z) * S;
+            double d = (double)xh - as_f64(xd[i]);
+            acc = __builtin_fma(as_f64(wd[i]), d * d, acc);
+        }
+    }
+    return acc;
+}
+
+template <int NT, int EPT, typename XT, bool PACKED>
+__device__ __forceinline__ double eval_fast_dispatch(bool check, bool err, const float (&u)[EPT],
+                                                     const XT (&xd)[EPT],
+                                                     const XT (&wd)[EPT], int n, int tid,
+                                                     float P, float S, float Z, uint32_t* hist,
+                                                     int base) {
+    if (check) {
+        if (err) return eval_fast<NT, EPT, XT, PACKED, true, true>(u, xd, wd, n, tid, P, S, Z, hist, base);
+        return eval_fast<NT, EPT, XT, PACKED, true, false>(u, xd, wd, n, tid, P, S, Z, hist, base);
+    }
+    if (err) return eval_fast<NT, EPT, XT, PACKED, false, true>(u, xd, wd, n, tid, P, S, Z, hist, base);
+    return eval_fast<NT, EPT, XT, PACKED, false, false>(u, xd, wd, n, tid, P, S, Z, hist, base);
+}
+
+template <int NT, int EPT>
+__global__ __launch_bounds__(NT) void sweep_kernel(SweepParams p, const TileRef* __restrict__ tiles) {
+    constexpr int NW = NT / MGS_WAVE;
+    // per-element copies: FP64 when registers allow, else FP32 converted per use
+    using XT = typename std::conditional<(EPT <= 8), double, float>::type;
+    extern __shared__ uint32_t hist[];
+    __shared__ double lg[LGTAB];
+    __shared__ double errpart[MGS_MAX_BITS][NW];
+    __shared__ double bitpart[MGS_MAX_BITS][NW];
+    __shared__ float red_mn[NW], red_mx[NW];
+    __shared__ uint32_t red_bad[NW];
+    __shared__ float prmS[MGS_MAX_BITS], prmZ[MGS_MAX_BITS];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (MGS_WAVE - 1);
+    const int wave = tid / MGS_WAVE;
+
+    const double* __restrict__ lgt = p.lgtab;
+    for (int h = tid; h < LGTAB; h += NT) lg[h] = h <= p.lgtab_max ? lgt[h] : 0.0;
+
+    for (int64_t it = blockIdx.x; it < p.ntiles; it += gridDim.x) {
+        // ---- locate the tile
+        int t, c, g;
+        const SceneDesc* sc;
+        if (tiles) {
+            TileRef tr = tiles[it];
+            sc = &p.scenes[tr.scene];
+            t = tr.t;
+            c = tr.c;
+            g = tr.g;
+        } else {
+            sc = &p.scenes[0];
+            int64_t gpc = sc->gpc;
+            c = (int)(it / gpc);
+            int r = (int)(it - (int64_t)c * gpc);
+            t = 0;
+            while (t + 1 < sc->T && sc->gcum[t + 1] <= r) ++t;
+            g = r - sc->gcum[t];
+        }
+        const int64_t j0 = (int64_t)g * sc->G;
+        const int64_t krem = sc->k[t] - j0;
+        const int n = (int)(krem < sc->G ? krem : sc->G);
+        const int32_t* J = sc->kept + sc->koff[t] + j0;
+        const float* row = sc->attr + (int64_t)c * sc->ld;
+        const int64_t slot = ((int64_t)t * sc->C + c) * sc->gmaxn + g;
+        const int nb = sc->nb;
+        const bool check = n < NT * EPT;
+
+        // ---- gather values and weights, min / max, finiteness
+        float u[EPT];
+        XT xd[EPT], wd[EPT];
+        float mn = INFINITY, mx = -INFINITY;
+        uint32_t bad = 0;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            int j = i * NT + tid;
+            float x = 0.0f, w = 0.0f;
+            if (j < n) {
+                int32_t idx = J[j];
+                x = row[idx];
+                w = sc->imp[idx];
+                bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
+                mn = fminf(mn, x);
+                mx = fmaxf(mx, x);
+            }
+            xd[i] = (XT)x;
+            wd[i] = (XT)w;
+        }
+        mn = wave_min_f32(mn);
+        mx = wave_max_f32(mx);
+        bad = wave_or_u32(bad);
+        if (lane == 0) {
+            red_mn[wave] = mn;
+            red_mx[wave] = mx;
+            red_bad[wave] = bad;
+        }
+        __syncthreads();
+        mn = red_mn[0];
+        mx = red_mx[0];
+        bad = red_bad[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            mn = fminf(mn, red_mn[w]);
+            mx = fmaxf(mx, red_mx[w]);
+            bad |= red_bad[w];
+        }
+        const float R = mx - mn;
+        if (!finite_f32(R)) bad = 1;
+        if (tid == 0) {
+            sc->gmin[slot] = mn;
+            sc->gmax[slot] = mx;
+        }
+        if (bad || R == 0.0f) {
+            // non-finite group: NaN tables and the status flag; constant
+            // group: every code 0, zero loss and zero size.
+            if (tid < nb) {
+                sc->err[slot * nb + tid] = bad ? NAN : 0.0;
+                sc->bits[slot * nb + tid] = bad ? NAN : 0.0;
+                if (!bad && sc->hist) sc->hist[slot * sc->hist_bins + sc->hoff[tid]] = (uint32_t)n;
+            }
+            if (bad && tid == 0) atomicOr(&p.status->nonfinite, 1u);
+            __syncthreads();
+            continue;
+        }
+
+        // ---- per-b scale and zero point (literal FP32 definition)
+        if (tid < nb) {
+            float P = ldexpf(1.0f, sc->bl[tid]);
+            float S = R / P;
+            float Z = 0.0f;
+            if (S != 0.0f) {
+                float r = mx / S;
+                Z = __builtin_rintf(P - r);
+            }
+            prmS[tid] = S;
+            prmZ[tid] = Z;
+        }
+        for (int i = tid; i < MGS_MAX_BITS * NW; i += NT) (&bitpart[0][0])[i] = 0.0;
+        const bool fast = R >= ldexpf(1.0f, sc->bmax - 126);
+        if (fast) {
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) u[i] = (float)xd[i] / R;
+        } else {
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) u[i] = 0.0f;
+        }
+        __syncthreads();
+
+        // ---- histogram batches
+        for (int bt = 0; bt < p.nbatches; ++bt) {
+            const int e0 = p.batch_begin[bt], e1 = p.batch_begin[bt + 1];
+            const int words = p.batch_words[bt];
+            for (int w = tid; w < words; w += NT) hist[w] = 0u;
+            __syncthreads();
+            for (int e = e0; e < e1; ++e) {
+                const HistEntry en = p.entries[e];
+                const int bi = en.bi;
+                const float S = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmS[bi])));
+                const float Z = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmZ[bi])));
+                const float P = ldexpf(1.0f, sc->bl[bi]);
+                const int base = en.lds_off - en.lo;
+                double acc = 0.0;
+                if (S == 0.0f) {
+                    // the range underflows at this b: every code is 0, xhat = min
+                    if (en.lo == 0 && tid == 0) hist[en.lds_off] += (uint32_t)n;
+                    if (en.first) {
+#pragma unroll
+                        for (int i = 0; i < EPT; ++i) {
+                            if (i * NT + tid < n) {
+                                double d = (double)mn - as_f64(xd[i]);
+                                acc = __builtin_fma(as_f64(wd[i]), d * d, acc);
+                            }
+                        }
+                    }
+                } else if (fast && !en.split && fabsf(Z) <= 8388608.0f) {
+                    if (en.packed)
+                        acc = eval_fast_dispatch<NT, EPT, XT, true>(check, en.first, u, xd, wd, n, tid,
+                                                                P, S, Z, hist, base);
+                    else
+                        acc = eval_fast_dispatch<NT, EPT, XT, false>(check, en.first, u, xd, wd, n, tid,
+                                                                 P, S, Z, hist, base);
+                } else {
+                    acc = eval_generic<NT, EPT, XT>(u, xd, wd, n, tid, P, S, Z, hist, base, en.lo,
+                                                en.nwords, en.packed, !fast, en.first);
+                }
+                if (en.first) {
+                    acc = wave_sum_f64(acc);
+                    if (lane == 0) errpart[bi][wave] = acc;
+                }
+            }
+            __syncthreads();
+            // ---- entropy terms (and the optional debug copy of the bins)
+            for (int e = e0; e < e1; ++e) {
+                const HistEntry en = p.entries[e];
+                double s = 0.0;
+                uint32_t* hout = sc->hist ? sc->hist + slot * sc->hist_bins + sc->hoff[en.bi] : nullptr;
+                for (int w = tid; w < en.nwords; w += NT) {
+                    uint32_t v = hist[en.lds_off + w];
+                    if (!en.packed) {
+                        s += hlog2h(v, lg, lgt);
+                        if (hout) hout[en.lo + w] = v;
+                    } else {
+                        uint32_t h0 = v & 0xFFFFu, h1 = v >> 16;
+                        s += hlog2h(h0, lg, lgt) + hlog2h(h1, lg, lgt);
+                        if (hout) {
+                            hout[2 * (en.lo + w)] = h0;
+                            hout[2 * (en.lo + w) + 1] = h1;
+                        }
+                    }
+                }
+                s = wave_sum_f64(s);
+                if (lane == 0) bitpart[en.bi][wave] += s;
+            }
+            __syncthreads();
+        }
+
+        // ---- finalize the tile's table entries
+        if (tid < nb) {
+            double e = 0.0, s = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                e += errpart[tid][w];
+                s += bitpart[tid][w];
+            }
+            sc->err[slot * nb + tid] = e;
+            sc->bits[slot * nb + tid] = lgt[n] - s;
+        }
+        __syncthreads();
+    }
+}
+
+// Copies one scene descriptor (a by-value kernel argument) into device memory.
+__global__ void scene_copy_kernel(SceneDesc sd, SceneDesc* dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = sd;
+}
+
+// Empty slots (groups past ceil(k_t / G)) hold NaN; the debug histogram is
+// cleared; the status word is reset.
+__global__ void sweep_init_kernel(const SceneDesc* __restrict__ scenes, int count,
+                                  mgs_status_block* status, double* lgtab, int lgtab_max) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) status->nonfinite = 0u;
+    // h * log2(h) for every count a group can hold (FP64, 0 for h < 2)
+    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h <= lgtab_max; h += gridDim.x * blockDim.x) {
+        double dh = (double)h;
+        lgtab[h] = h < 2 ? 0.0 : dh * log2(dh);
+    }
+    for (int s = 0; s < count; ++s) {
+        const SceneDesc* sc = &scenes[s];
+        const int64_t nslot = (int64_t)sc->T * sc->C * sc->gmaxn;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslot;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            int t = (int)(i / ((int64_t)sc->C * sc->gmaxn));
+            int g = (int)(i % sc->gmaxn);
+            int ng = sc->gcum[t + 1] - sc->gcum[t];
+            if (g >= ng) {
+                for (int b = 0; b < sc->nb; ++b) {
+                    sc->err[i * sc->nb + b] = NAN;
+                    sc->bits[i * sc->nb + b] = NAN;
+                }
+                sc->gmin[i] = NAN;
+                sc->gmax[i] = NAN;
+            }
+            if (sc->hist)
+                for (int64_t b = 0; b < sc->hist_bins; ++b) sc->hist[i * sc->hist_bins + b] = 0u;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+template <int NT, int EPT>
+static hipError_t launch_one(const SweepParams& p, const TileRef* tiles, int64_t grid, size_t lds,
+                             hipStream_t s) {
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel<NT, EPT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)e;
+    }
+    hipLaunchKernelGGL((sweep_kernel<NT, EPT>), dim3((unsigned)grid), dim3(NT), lds, s, p, tiles);
+    return hipGetLastError();
+}
+
+struct Variant {
+    int nt, ept;
+    hipError_t (*fn)(const SweepParams&, const TileRef*, int64_t, size_t, hipStream_t);
+    const void* kern;
+};
+
+#define MGS_V(NT, EPT) {NT, EPT, &launch_one<NT, EPT>, (const void*)&sweep_kernel<NT, EPT>}
+static const Variant kVariants[] = {
+    MGS_V(256, 1),  MGS_V(256, 2),  MGS_V(256, 4),  MGS_V(256, 8),  MGS_V(256, 16), MGS_V(256, 32),
+    MGS_V(512, 1),  MGS_V(512, 2),  MGS_V(512, 4),  MGS_V(512, 8),  MGS_V(512, 16), MGS_V(512, 32),
+    MGS_V(1024, 1), MGS_V(1024, 2), MGS_V(1024, 4), MGS_V(1024, 8), MGS_V(1024, 16),
+};
+#undef MGS_V
+
+static const Variant* find_variant(int nt, int ept) {
+    for (const Variant& v : kVariants)
+        if (v.nt == nt && v.ept == ept) return &v;
+    return nullptr;
+}
+
+int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+Shape variant_shape(int i) { return Shape{kVariants[i].nt, kVariants[i].ept, 0}; }
+
+static int device_attr(hipDeviceAttribute_t a, int fallback) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fallback;
+    if (hipDeviceGetAttribute(&v, a, dev) != hipSuccess || v <= 0) return fallback;
+    return v;
+}
+
+static int device_lds_bytes() {
+    static int cached = 0;
+    if (!cached) cached = device_attr(hipDeviceAttributeMaxSharedMemoryPerBlock, 65536);
+    return cached;
+}
+
+int device_cus() {
+    static int cached = 0;
+    if (!cached) cached = device_attr(hipDeviceAttributeMultiprocessorCount, 256);
+    return cached;
+}
+
+// Static LDS of a kernel variant (everything but the histogram words).
+static int static_lds_bytes(int nt) {
+    int nw = nt / MGS_WAVE;
+    return (int)(sizeof(double) * LGTAB + 2 * sizeof(double) * MGS_MAX_BITS * nw + 3 * 4 * nw +
+                 2 * 4 * MGS_MAX_BITS) + 256;
+}
+
+bool build_plan(const uint8_t* bl, int nb, int cap_words, SweepParams* p) {
+    // Greedy: largest histograms first, each into the first batch with room;
+    // a b larger than a whole batch is split into windows of cap_words.
+    struct Item { int bi; int words; bool packed; };
+    std::vector<Item> items;
+    for (int i = 0; i < nb; ++i) {
+        int full = 1 << bl[i];
+        bool packed = full > cap_words;
+        items.push_back({i, packed ? full / 2 : full, packed});
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item& a, const Item& c) { return a.words > c.words; });
+    std::vector<std::vector<HistEntry>> batches;
+    std::vector<int> used;
+    for (const Item& it : items) {
+        if (it.words > cap_words) {
+            for (int lo = 0; lo < it.words; lo += cap_words) {
+                HistEntry e{};
+                e.bi = (int16_t)it.bi;
+                e.packed = it.packed;
+                e.first = lo == 0;
+                e.split = 1;
+                e.lo = lo;
+                e.nwords = std::min(cap_words, it.words - lo);
+                e.lds_off = 0;
+                batches.push_back({e});
+                used.push_back(e.nwords);
+            }
+            continue;
+        }
+        size_t k = 0;
+        for (; k < batches.size(); ++k)
+            if (used[k] + it.words <= cap_words) break;
+        if (k == batches.size()) {
+            batches.push_back({});
+            used.push_back(0);
+        }
+        HistEntry e{};
+        e.bi = (int16_t)it.bi;
+        e.packed = it.packed;
+        e.first = 1;
+        e.split = 0;
+        e.lo = 0;
+        e.nwords = it.words;
+        e.lds_off = used[k];
+        used[k] += it.words;
+        batches[k].push_back(e);
+    }
+    int ne = 0;
+    for (auto& b : batches) ne += (int)b.size();
+    if (ne > MGS_MAX_ENTRIES || (int)batches.size() > MGS_MAX_ENTRIES) return false;
+    p->nbatches = (int)batches.size();
+    p->nentries = ne;
+    p->max_batch_words = 0;
+    int e = 0;
+    for (size_t k = 0; k < batches.size(); ++k) {
+        p->batch_begin[k] = e;
+        p->batch_words[k] = used[k];
+        p->max_batch_words = std::max(p->max_batch_words, used[k]);
+        for (const HistEntry& he : batches[k]) p->entries[e++] = he;
+    }
+    p->batch_begin[batches.size()] = e;
+    return true;
+}
+
+int plan_for(const SceneDesc& sc, const Shape& sh, SweepParams* p, size_t* lds_bytes) {
+    int devlds = device_lds_bytes();
+    int cap = sh.lds_cap > 0 ? std::min(sh.lds_cap, devlds) : devlds;
+    int cap_words = (cap - static_lds_bytes(sh.nt)) / 4;
+    // keep the capacity a power of two so bin windows tile 2^b evenly
+    int pw = 1024;
+    while (pw * 2 <= cap_words) pw *= 2;
+    if (!build_plan(sc.bl, sc.nb, pw, p)) return MGS_EINVAL;
+    *lds_bytes = (size_t)p->max_batch_words * 4;
+    return MGS_OK;
+}
+
+int fill_scene(const mgs_sweep_desc* d, const float* attr, const float* imp, const int32_t* kept,
+               double* err, double* bits, float* gmin, float* gmax, uint32_t* hist, SceneDesc* sc) {
+    if (!d || !d->h_k || !d->h_bits) return MGS_EINVAL;
+    if (d->C < 1 || d->T < 1 || d->T > MGS_MAX_RATIOS || d->G < 1 || d->G > MGS_MAX_GROUP ||
+        d->nb < 1 || d->nb > MGS_MAX_BITS || d->N < 0 || d->N >= ((int64_t)1 << 31) || d->ld < d->N)
+        return MGS_EINVAL;
+    for (int i = 0; i < d->nb; ++i) {
+        if (d->h_bits[i] < 1 || d->h_bits[i] > MGS_MAX_BITS) return MGS_EINVAL;
+        if (i && d->h_bits[i] <= d->h_bits[i - 1]) return MGS_EINVAL;
+    }
+    std::memset(sc, 0, sizeof(*sc));
+    int64_t kmax = 0, off = 0;
+    int64_t gc = 0;
+    for (int t = 0; t < d->T; ++t) {
+        int64_t k = d->h_k[t];
+        if (k < 0 || k > d->N) return MGS_EINVAL;
+        sc->k[t] = k;
+        sc->koff[t] = off;
+        off += k;
+        kmax = std::max(kmax, k);
+        sc->gcum[t] = (int32_t)gc;
+        gc += (k + d->G - 1) / d->G;
+    }
+    if (gc >= ((int64_t)1 << 31) / d->C) return MGS_EINVAL;
+    sc->gcum[d->T] = (int32_t)gc;
+    if (off > 0 && (!kept || !imp || !attr)) return MGS_EINVAL;
+    if (!err || !bits || !gmin || !gmax) return MGS_EINVAL;
+    sc->attr = attr;
+    sc->imp = imp;
+    sc->kept = kept;
+    sc->err = err;
+    sc->bits = bits;
+    sc->gmin = gmin;
+    sc->gmax = gmax;
+    sc->hist = hist;
+    sc->ld = d->ld;
+    sc->C = d->C;
+    sc->T = d->T;
+    sc->G = d->G;
+    sc->nb = d->nb;
+    sc->gmaxn = (int32_t)((kmax + d->G - 1) / d->G);
+    sc->gpc = (int32_t)gc;
+    sc->bmax = d->h_bits[d->nb - 1];
+    int64_t hb = 0;
+    for (int i = 0; i < d->nb; ++i) {
+        sc->bl[i] = d->h_bits[i];
+        sc->hoff[i] = hb;
+        hb += (int64_t)1 << d->h_bits[i];
+    }
+    sc->hist_bins = hb;
+    return MGS_OK;
+}
+
+bool shape_valid(const Shape& sh, int G) {
+    return find_variant(sh.nt, sh.ept) != nullptr && (int64_t)sh.nt * sh.ept >= G;
+}
+
+// Default launch shape: the fewest elements per thread that still gives each
+// thread >= 8 of them (or the largest workgroup when G is small).
+Shape default_shape(int G, int nb, int bmax) {
+    (void)nb;
+    (void)bmax;
+    for (int e : {8, 16, 4, 2, 1, 32}) {
+        for (int t : {256, 512, 1024}) {
+            if ((int64_t)t * e >= G && find_variant(t, e)) return Shape{t, e, 0};
+        }
+    }
+    return Shape{0, 0, 0};
+}
+
+int launch_sweep(const SweepParams& p, const TileRef* tiles, const Shape& sh, size_t lds,
+                 int64_t grid, hipStream_t s) {
+    const Variant* v = find_variant(sh.nt, sh.ept);
+    if (!v) return MGS_EINVAL;
+    if (grid <= 0 || grid > p.ntiles) grid = p.ntiles;
+    if (grid < 1) return MGS_OK;
+    if (grid > 0x7fffffff) grid = 0x7fffffff;
+    return v->fn(p, tiles, grid, lds, s) == hipSuccess ? MGS_OK : MGS_EDEVICE;
+}
+
+int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
+                mgs_status_block* status, double* lgtab, int lgtab_max, hipStream_t s) {
+    int64_t slots = 0;
+    for (int i = 0; i < count; ++i) {
+        hipLaunchKernelGGL(scene_copy_kernel, dim3(1), dim3(64), 0, s, host_scenes[i], d_scenes + i);
+        slots = std::max(slots, (int64_t)host_scenes[i].T * host_scenes[i].C * host_scenes[i].gmaxn);
+    }
+    int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((slots + 255) / 256, 2048));
+    blocks = std::max<int64_t>(blocks, (lgtab_max + 256) / 256);
+    blocks = std::min<int64_t>(blocks, 2048);
+    hipLaunchKernelGGL(sweep_init_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_scenes, count,
+                       status, lgtab, lgtab_max);
+    return mgs_last_launch();
+}
+
+int max_resident_blocks(const Shape& sh, size_t lds) {
+    const Variant* v = find_variant(sh.nt, sh.ept);
+    if (!v) return 1;
+    int nblk = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, v->kern, sh.nt, lds) != hipSuccess ||
+        nblk < 1)
+        nblk = 1;
+    return nblk;
+}
+
+// ------------------------------------------------------------------ autotune registry
+
+namespace {
+struct TunedEntry { int G, nb, bmax; Shape sh; };
+std::mutex g_tune_mu;
+std::vector<TunedEntry> g_tuned;
+}  // namespace
+
+bool tuned_shape(int G, int nb, int bmax, Shape* out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TunedEntry& e : g_tuned)
+        if (e.G == G && e.nb == nb && e.bmax == bmax) {
+            *out = e.sh;
+            return true;
+        }
+    return false;
+}
+
+void set_tuned_shape(int G, int nb, int bmax, const Shape& sh) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (TunedEntry& e : g_tuned)
+        if (e.G == G && e.nb == nb && e.bmax == bmax) {
+            e.sh = sh;
+            return;
+        }
+    g_tuned.push_back({G, nb, bmax, sh});
+}
+
+}  // namespace mgs
+
+// ------------------------------------------------------------------ C ABI
+
+// Workspace: status word | scene descriptor | h log2 h table [0, G].
+static size_t sweep_ws_scene_off() { return MGS_STATUS_BYTES; }
+static size_t sweep_ws_table_off() {
+    return sweep_ws_scene_off() + mgs_align_up(sizeof(mgs::SceneDesc), 256);
+}
+
+extern "C" size_t mgs_quant_sweep_ws_bytes(const mgs_sweep_desc* desc) {
+    int G = desc ? desc->G : MGS_MAX_GROUP;
+    if (G < 1 || G > MGS_MAX_GROUP) G = MGS_MAX_GROUP;
+    return sweep_ws_table_off() + mgs_align_up(sizeof(double) * ((size_t)G + 1), 256);
+}
+
+extern "C" int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                               const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                               float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes,
+                               void* stream) {
+    using namespace mgs;
+    SceneDesc sc;
+    int rc = fill_scene(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, d_hist, &sc);
+    if (rc) return rc;
+    if (!d_ws || ws_bytes < mgs_quant_sweep_ws_bytes(desc)) return MGS_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Shape sh;
+    if (!tuned_shape(sc.G, sc.nb, sc.bmax, &sh) || !shape_valid(sh, sc.G))
+        sh = default_shape(sc.G, sc.nb, sc.bmax);
+    if (!shape_valid(sh, sc.G)) return MGS_EINVAL;
+    SweepParams p;
+    std::memset(&p, 0, sizeof(p));
+    size_t lds = 0;
+    rc = plan_for(sc, sh, &p, &lds);
+    if (rc) return rc;
+    auto* status = (mgs_status_block*)d_ws;
+    auto* d_sc = (SceneDesc*)((char*)d_ws + sweep_ws_scene_off());
+    auto* lgtab = (double*)((char*)d_ws + sweep_ws_table_off());
+    rc = launch_init(&sc, 1, d_sc, status, lgtab, sc.G, s);
+    if (rc) return rc;
+    p.status = status;
+    p.scenes = d_sc;
+    p.lgtab = lgtab;
+    p.lgtab_max = sc.G;
+    p.ntiles = (int64_t)sc.C * sc.gpc;
+    if (p.ntiles == 0) return MGS_OK;
+    return launch_sweep(p, nullptr, sh, lds, 0, s);
+}

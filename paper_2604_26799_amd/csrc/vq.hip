@@ -1,0 +1,376 @@
+// Nearest-codeword assignment of the vector quantizer for the higher-degree
+// SH coefficients.  Paper: section "Attribute Transformation", clustering of
+// the 1+D SH coefficients (a codebook plus an index mapping table, refined by
+// mini-batch k-means whose inner step is this assignment).
+//
+// Definition: idx_i = argmin_j sum_d (x_id - c_jd)^2 with the distance summed
+// in FP64 over d in order; ties -> smallest j.
+//
+// Method.  argmin_j ||x - c_j||^2 = argmin_j s_j with s_j = ||c_j||^2 - 2 x.c_j.
+//   1. Scores s~_j from BF16 MFMA (v_mfma_f32_32x32x16_bf16, FP32
+//      accumulation).  The codeword tile is the A operand (32 codewords x 16
+//      dims), the X tile the B operand (16 dims x 32 rows), so each lane owns
+//      one row and 16 codewords of every 32x32 output tile and keeps its
+//      running minimum without cross-lane work.  ||c_j||^2 enters as two
+//      extra K columns (its BF16 high and low parts) against constant 1s in X.
+//   2. Error bound per row: |s~_j - s_j| <= E_i with
+//        E_i = 2(2u+u^2)|x_i| cmax + 2^-15 cmax^2 + g (2.02 |x_i| cmax + 1.01 cmax^2)
+//      (u = 2^-8 BF16 rounding, g = (D+3) 2^-23 for any FP32 accumulation
+//      order).  The exact winner then satisfies s~_j <= min s~ + 2 E_i; a
+//      small FP64 slack 2 delta_i also admits the winner of the FP64
+//      definition when exact distances tie within FP64 rounding.
+//   3. Each lane keeps up to 8 candidates (s~ <= its running min + T_i);
+//      at the end the row's candidates under the final threshold are
+//      re-scored with the FP64 definition (same operation order) and the
+//      smallest (distance, index) wins.  Rows whose buffer overflowed go to
+//      an exact FP64 full scan.
+// The result equals the FP64 definition bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace mgs {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int VQ_WAVES = 4;
+constexpr int VQ_THREADS = VQ_WAVES * MGS_WAVE;
+constexpr int VQ_ROWSETS = 2;                          // 32-row sets per wave
+constexpr int VQ_ROWS = VQ_WAVES * VQ_ROWSETS * 32;    // rows per workgroup
+constexpr int VQ_CHUNK = 256;                          // codewords per LDS chunk
+constexpr int VQ_CAND = 8;                             // candidate slots per lane and row set
+constexpr int VQ_KS_MAX = 5;                           // 16-wide K steps (D + 2 <= 80)
+
+struct VqArgs {
+    const float* x;
+    const float* cb;
+    int32_t* idx;
+    double* dist;
+    int64_t* nfb_out;
+    mgs_status_block* status;
+    __bf16* cbp;          // [Kpad][KP] prepared codebook (-2c, ||c||^2 hi, lo, 0 pad)
+    uint32_t* cmax_bits;  // max codeword norm, FP32 bits (rounded up)
+    uint32_t* fb_count;
+    int32_t* fb_list;
+    int64_t N;
+    int32_t D, K, Kpad, KP;
+};
+
+// Prepared codebook and the codeword-norm maximum (the status word, the
+// maximum and the fallback counter are cleared before this kernel).
+__global__ void vq_prep_kernel(VqArgs a) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.Kpad) return;
+    __bf16* row = a.cbp + (int64_t)j * a.KP;
+    if (j >= a.K) {
+        for (int k = 0; k < a.KP; ++k) row[k] = (__bf16)0.0f;
+        row[a.D] = (__bf16)1.0e30f;  // padding codewords score ~1e30 and are skipped
+        return;
+    }
+    const float* c = a.cb + (int64_t)j * a.D;
+    double n2 = 0.0;
+    bool bad = false;
+    for (int k = 0; k < a.D; ++k) {
+        float v = c[k];
+        bad |= !finite_f32(v);
+        n2 += (double)v * (double)v;
+        row[k] = (__bf16)(-2.0f * v);
+    }
+    float hi = (float)(__bf16)(float)n2;
+    float lo = (float)(n2 - (double)hi);
+    row[a.D] = (__bf16)hi;
+    row[a.D + 1] = (__bf16)lo;
+    for (int k = a.D + 2; k < a.KP; ++k) row[k] = (__bf16)0.0f;
+    if (bad) atomicOr(&a.status->nonfinite, 1u);
+    float nrm = (float)sqrt(n2) * (1.0f + 1.0e-6f);
+    atomicMax(a.cmax_bits, __float_as_uint(nrm));  // non-negative floats order as uints
+}
+
+__device__ __forceinline__ double exact_dist(const float* __restrict__ x, const float* __restrict__ c,
+                                             int D) {
+    double s = 0.0;
+    for (int k = 0; k < D; ++k) {
+        double d = (double)x[k] - (double)c[k];
+        s += d * d;
+    }
+    return s;
+}
+
+template <int KS>
+__global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
+    constexpr int KP = 16 * KS;
+    constexpr int LDS_STRIDE = KP + 8;  // bf16 elements; padding spreads LDS banks
+    __shared__ __attribute__((aligned(16))) __bf16 cbs[VQ_CHUNK * LDS_STRIDE];
+    __shared__ float cand_s[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
+    __shared__ int32_t cand_j[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5;  // which 8 of each 16 dims / which 4-row blocks of the output
+    const int D = a.D, K = a.K;
+    const int64_t row0 = (int64_t)blockIdx.x * VQ_ROWS + wave * (VQ_ROWSETS * 32);
+
+    // ---- B operands (the X rows), bound T per row
+    bf16x8 breg[VQ_ROWSETS][KS];
+    float T[VQ_ROWSETS];
+    int64_t rows[VQ_ROWSETS];
+    uint32_t bad = 0;
+    const float cm = __uint_as_float(*a.cmax_bits);
+#pragma unroll
+    for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
+        const int64_t r = row0 + rs * 32 + (lane & 31);
+        rows[rs] = r;
+        float n2 = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = 16 * ks + 8 * half + i;
+                float v = 0.0f;
+                if (r < a.N) {
+                    if (k < D) {
+                        v = a.x[r * D + k];
+                        bad |= (uint32_t)!finite_f32(v);
+                        n2 += v * v;
+                    } else if (k == D || k == D + 1) {
+                        v = 1.0f;
+                    }
+                }
+                breg[rs][ks][i] = (__bf16)v;
+            }
+        }
+        n2 += __shfl_xor(n2, 32, MGS_WAVE);
+        const double xn = sqrt((double)n2) * (1.0 + 1.0e-5) + 1e-30;
+        const double u = 1.0 / 256.0;
+        const double g = (double)(D + 3) * 0x1p-23;
+        const double E = 2.0 * (2.0 * u + u * u) * xn * cm + 0x1p-15 * (double)cm * cm +
+                         g * (2.02 * xn * cm + 1.01 * (double)cm * cm);
+        const double delta = 2.0 * (D + 2) * 0x1p-52 * (xn + cm) * (xn + cm);
+        const double scale = (double)cm * cm + 2.0 * xn * cm;
+        T[rs] = (float)((2.0 * E + 2.0 * delta) * 1.0001 + 1.0e-6 * scale + 1e-30);
+    }
+    if (bad) atomicOr(&a.status->nonfinite, 1u);
+
+    float mhalf[VQ_ROWSETS];
+    int cnt[VQ_ROWSETS];
+    int ovf[VQ_ROWSETS];
+#pragma unroll
+    for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
+        mhalf[rs] = INFINITY;
+        cnt[rs] = 0;
+        ovf[rs] = 0;
+    }
+
+    const int units_per_row = KP / 8;  // 16-byte units
+    for (int c0 = 0; c0 < a.Kpad; c0 += VQ_CHUNK) {
+        const int nrows = min(VQ_CHUNK, a.Kpad - c0);
+        __syncthreads();
+        for (int uidx = tid; uidx < nrows * units_per_row; uidx += VQ_THREADS) {
+            const int r = uidx / units_per_row, part = uidx - r * units_per_row;
+            const uint4 v = *(const uint4*)(a.cbp + (int64_t)(c0 + r) * KP + part * 8);
+            *(uint4*)(cbs + r * LDS_STRIDE + part * 8) = v;
+        }
+        __syncthreads();
+        for (int tile = 0; tile < nrows / 32; ++tile) {
+            bf16x8 areg[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                areg[ks] = *(const bf16x8*)(cbs + (tile * 32 + (lane & 31)) * LDS_STRIDE + 16 * ks + 8 * half);
+            const int jbase = c0 + tile * 32;
+#pragma unroll
+            for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
+                f32x16 acc = {};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(areg[ks], breg[rs][ks], acc, 0, 0, 0);
+                float tmin = acc[0];
+#pragma unroll
+                for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[i]);
+                mhalf[rs] = fminf(mhalf[rs], tmin);
+                const float thr = mhalf[rs] + T[rs];
+                if (tmin <= thr && !ovf[rs]) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const float s = acc[i];
+                        // output element i of this lane: codeword row 8*(i/4) + 4*half + i%4
+                        const int j = jbase + 8 * (i >> 2) + 4 * half + (i & 3);
+                        if (s <= thr && j < K && !ovf[rs]) {
+                            if (cnt[rs] == VQ_CAND) {
+                                int w = 0;
+                                for (int e = 0; e < VQ_CAND; ++e) {
+                                    float se = cand_s[wave][rs][e][lane];
+                                    if (se <= thr) {
+                                        cand_s[wave][rs][w][lane] = se;
+                                        cand_j[wave][rs][w][lane] = cand_j[wave][rs][e][lane];
+                                        ++w;
+                                    }
+                                }
+                                cnt[rs] = w;
+                                if (w == VQ_CAND) ovf[rs] = 1;
+                            }
+                            if (!ovf[rs]) {
+                                cand_s[wave][rs][cnt[rs]][lane] = s;
+                                cand_j[wave][rs][cnt[rs]][lane] = j;
+                                cnt[rs] += 1;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- exact FP64 re-rank of the row's candidates (both lanes of the row)
+#pragma unroll
+    for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
+        const int64_t r = rows[rs];
+        const float mrow = fminf(mhalf[rs], __shfl_xor(mhalf[rs], 32, MGS_WAVE));
+        const float thr = mrow + T[rs];
+        const int ovf_row = ovf[rs] | __shfl_xor(ovf[rs], 32, MGS_WAVE);
+        double best = INFINITY;
+        int32_t bj = 0x7fffffff;
+        if (r < a.N && !ovf_row) {
+            const float* xr = a.x + r * D;
+            for (int e = 0; e < cnt[rs]; ++e) {
+                if (cand_s[wave][rs][e][lane] <= thr) {
+                    const int32_t j = cand_j[wave][rs][e][lane];
+                    const double d = exact_dist(xr, a.cb + (int64_t)j * D, D);
+                    if (d < best || (d == best && j < bj)) {
+                        best = d;
+                        bj = j;
+                    }
+                }
+            }
+        }
+        const double ob = __shfl_xor(best, 32, MGS_WAVE);
+        const int32_t oj = __shfl_xor(bj, 32, MGS_WAVE);
+        if (ob < best || (ob == best && oj < bj)) {
+            best = ob;
+            bj = oj;
+        }
+        if (r < a.N && half == 0) {
+            if (ovf_row) {
+                a.fb_list[atomicAdd(a.fb_count, 1u)] = (int32_t)r;
+            } else {
+                a.idx[r] = bj;
+                if (a.dist) a.dist[r] = best;
+            }
+        }
+    }
+}
+
+// Exact FP64 full scan for the rows whose candidate buffer overflowed: one
+// wavefront per row, lanes stride over the codewords.
+__global__ __launch_bounds__(256) void vq_fallback_kernel(VqArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const uint32_t total = *a.fb_count;
+    if (a.nfb_out && blockIdx.x == 0 && threadIdx.x == 0) *a.nfb_out = (int64_t)total;
+    for (int64_t i = wid; i < total; i += nw) {
+        const int32_t r = a.fb_list[i];
+        const float* xr = a.x + (int64_t)r * a.D;
+        double best = INFINITY;
+        int32_t bj = 0x7fffffff;
+        for (int j = lane; j < a.K; j += 64) {
+            const double d = exact_dist(xr, a.cb + (int64_t)j * a.D, a.D);
+            if (d < best) {  // j increases per lane: strict < keeps the smallest j
+                best = d;
+                bj = j;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ob = __shfl_xor(best, o, MGS_WAVE);
+            const int32_t oj = __shfl_xor(bj, o, MGS_WAVE);
+            if (ob < best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        if (lane == 0) {
+            a.idx[r] = bj;
+            if (a.dist) a.dist[r] = best;
+        }
+    }
+}
+
+struct VqLayout {
+    size_t cmax, cbp, fb, total;
+    int KS, KP, Kpad;
+};
+
+VqLayout vq_layout(int64_t N, int D, int K) {
+    VqLayout L;
+    L.KS = (D + 2 + 15) / 16;
+    L.KP = 16 * L.KS;
+    L.Kpad = (int)(((int64_t)K + 31) / 32 * 32);
+    size_t o = MGS_STATUS_BYTES;
+    L.cmax = o;
+    o += 256;
+    L.cbp = o;
+    o += mgs_align_up(sizeof(__bf16) * (size_t)L.Kpad * L.KP, 256);
+    L.fb = o;
+    o += mgs_align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(N, 1), 256);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+}  // namespace mgs
+
+extern "C" size_t mgs_vq_assign_ws_bytes(int64_t N, int32_t D, int32_t K) {
+    if (N < 0 || D < 1 || D > MGS_MAX_VQ_DIM || K < 1) return 0;
+    return mgs::vq_layout(N, D, K).total;
+}
+
+extern "C" int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float* d_cb, int32_t K,
+                             int32_t* d_idx, double* d_dist, int64_t* d_nfallback, void* d_ws,
+                             size_t ws_bytes, void* stream) {
+    using namespace mgs;
+    if (N < 0 || N >= ((int64_t)1 << 31) || D < 1 || D > MGS_MAX_VQ_DIM || K < 1 || !d_cb)
+        return MGS_EINVAL;
+    if (N > 0 && (!d_x || !d_idx)) return MGS_EINVAL;
+    VqLayout L = vq_layout(N, D, K);
+    if (!d_ws || ws_bytes < L.total) return MGS_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    VqArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.x = d_x;
+    a.cb = d_cb;
+    a.idx = d_idx;
+    a.dist = d_dist;
+    a.nfb_out = d_nfallback;
+    a.status = (mgs_status_block*)ws;
+    a.cmax_bits = (uint32_t*)(ws + L.cmax);
+    a.fb_count = (uint32_t*)(ws + L.cmax + 64);
+    a.cbp = (__bf16*)(ws + L.cbp);
+    a.fb_list = (int32_t*)(ws + L.fb);
+    a.N = N;
+    a.D = D;
+    a.K = K;
+    a.Kpad = L.Kpad;
+    a.KP = L.KP;
+    int rc = mgs_fill<uint32_t>((uint32_t*)ws, 64, 0u, s);       // status word
+    if (rc) return rc;
+    rc = mgs_fill<uint32_t>(a.cmax_bits, 64, 0u, s);              // norm maximum + fallback count
+    if (rc) return rc;
+    hipLaunchKernelGGL(vq_prep_kernel, dim3((L.Kpad + 255) / 256), dim3(256), 0, s, a);
+    if (N > 0) {
+        const unsigned blocks = (unsigned)((N + VQ_ROWS - 1) / VQ_ROWS);
+        switch (L.KS) {
+            case 1: hipLaunchKernelGGL(vq_main_kernel<1>, dim3(blocks), dim3(VQ_THREADS), 0, s, a); break;
+            case 2: hipLaunchKernelGGL(vq_main_kernel<2>, dim3(blocks), dim3(VQ_THREADS), 0, s, a); break;
+            case 3: hipLaunchKernelGGL(vq_main_kernel<3>, dim3(blocks), dim3(VQ_THREADS), 0, s, a); break;
+            case 4: hipLaunchKernelGGL(vq_main_kernel<4>, dim3(blocks), dim3(VQ_THREADS), 0, s, a); break;
+            default: hipLaunchKernelGGL(vq_main_kernel<5>, dim3(blocks), dim3(VQ_THREADS), 0, s, a); break;
+        }
+    }
+    hipLaunchKernelGGL(vq_fallback_kernel, dim3(512), dim3(256), 0, s, a);
+    return mgs_last_launch();
+}

@@ -1,0 +1,276 @@
+"""ctypes binding of libmgs (the C ABI in include/mgs.h).
+
+Argument marshalling only: every step runs in the library (HIP kernels on the
+GPU, the 0-1 ILP on the host).  PyTorch supplies device memory and the
+current stream.  If the library is missing this module raises; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgs.so")
+
+OK, EINVAL, ENONFINITE, EINFEASIBLE, EDEVICE, EWORKSPACE, ELIMIT = 0, -1, -2, -3, -4, -5, -6
+MAX_RATIOS, MAX_GROUP, MAX_BITS, MAX_VQ_DIM = 64, 65535, 16, 64
+
+_lib = None
+
+
+class MgsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class SweepDesc(ct.Structure):
+    _fields_ = [("N", ct.c_int64), ("ld", ct.c_int64), ("C", ct.c_int32), ("T", ct.c_int32),
+                ("G", ct.c_int32), ("nb", ct.c_int32), ("h_k", ct.c_void_p), ("h_bits", ct.c_void_p)]
+
+
+# name -> (restype, argtypes); the full exported surface of include/mgs.h
+P, I32, I64, SZ, D = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t, ct.c_double
+SIGNATURES = {
+    "mgs_strerror": (ct.c_char_p, [ct.c_int]),
+    "mgs_version": (ct.c_char_p, []),
+    "mgs_status_fetch": (ct.c_int, [P, P]),
+    "mgs_prune_select_ws_bytes": (SZ, [I64, I32]),
+    "mgs_prune_select": (ct.c_int, [P, I64, P, I32, P, P, SZ, P]),
+    "mgs_quant_sweep_ws_bytes": (SZ, [P]),
+    "mgs_quant_sweep": (ct.c_int, [P, P, P, P, P, P, P, P, P, P, SZ, P]),
+    "mgs_quantize": (ct.c_int, [P, I64, I32, P, I64, I32, P, P, P, P, P]),
+    "mgs_dequantize": (ct.c_int, [P, I64, I32, I32, P, P, P, P, P]),
+    "mgs_vq_assign_ws_bytes": (SZ, [I64, I32, I32]),
+    "mgs_vq_assign": (ct.c_int, [P, I64, I32, P, I32, P, P, P, P, SZ, P]),
+    "mgs_ilp_solve": (ct.c_int, [P, P, I64, I32, I64, P, P, P]),
+    "mgs_size_table": (ct.c_int, [P, P, I64, I32, P, I32, P]),
+    "mgs_search": (ct.c_int, [P, P, P, I64, I32, I32, P, P, P, P]),
+}
+
+
+def lib():
+    """Load libmgs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libmgs.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ct.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().mgs_strerror(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise MgsError(code, what)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+# ----------------------------------------------------------------- device side
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t) -> int:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def workspace(nbytes: int, device=None):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def status(ws, stream=None) -> int:
+    return lib().mgs_status_fetch(_dptr(ws), _stream(stream))
+
+
+def _finish(ws, check: bool, what: str, stream=None):
+    if check:
+        code = status(ws, stream)
+        if code != OK:
+            raise MgsError(code, what)
+
+
+def prune_select(imp, k: Sequence[int], ws=None, out=None, stream=None, check: bool = True):
+    """Kept indices (int32, concatenated per ratio, each ascending) on the device."""
+    torch = _torch()
+    k = np.ascontiguousarray(k, dtype=np.int64)
+    n = imp.numel()
+    need = lib().mgs_prune_select_ws_bytes(n, k.size)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, imp.device)
+    if out is None:
+        out = torch.empty(int(k.sum()), dtype=torch.int32, device=imp.device)
+    _check(lib().mgs_prune_select(_dptr(imp), n, _np_ptr(k), k.size, _dptr(out) if out.numel() else None,
+                                  _dptr(ws), ws.numel(), _stream(stream)), "mgs_prune_select")
+    _finish(ws, check, "mgs_prune_select", stream)
+    return out
+
+
+def sweep_desc(N: int, C: int, k, G: int, bits, ld: Optional[int] = None):
+    k = np.ascontiguousarray(k, dtype=np.int64)
+    bl = np.ascontiguousarray(bits, dtype=np.uint8)
+    d = SweepDesc(N, N if ld is None else ld, C, k.size, G, bl.size, k.ctypes.data, bl.ctypes.data)
+    d._keep = (k, bl)  # keep the host arrays alive with the descriptor
+    return d
+
+
+def gmax_groups(k, G: int) -> int:
+    return int((int(np.max(k)) + G - 1) // G)
+
+
+def quant_sweep(attr, imp, kept, k, G: int, bits, want_hist: bool = False, ws=None, out=None,
+                stream=None, check: bool = True):
+    """Loss / size tables ``err, bits [T][C][Gmax][nb]`` (FP64) and ``gmin, gmax`` (FP32)."""
+    torch = _torch()
+    C, N = attr.shape
+    d = sweep_desc(N, C, k, G, bits)
+    T, nb = d.T, d.nb
+    gm = gmax_groups(k, G)
+    dev = attr.device
+    need = lib().mgs_quant_sweep_ws_bytes(ct.byref(d))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    if out is None:
+        out = {
+            "err": torch.empty((T, C, gm, nb), dtype=torch.float64, device=dev),
+            "bits": torch.empty((T, C, gm, nb), dtype=torch.float64, device=dev),
+            "gmin": torch.empty((T, C, gm), dtype=torch.float32, device=dev),
+            "gmax": torch.empty((T, C, gm), dtype=torch.float32, device=dev),
+            "hist": None,
+        }
+        if want_hist:
+            hb = int(sum(1 << int(b) for b in d._keep[1]))
+            out["hist"] = torch.empty((T, C, gm, hb), dtype=torch.int32, device=dev)
+    _check(lib().mgs_quant_sweep(ct.byref(d), _dptr(attr), _dptr(imp), _dptr(kept) if kept.numel() else None,
+                                 _dptr(out["err"]), _dptr(out["bits"]), _dptr(out["gmin"]),
+                                 _dptr(out["gmax"]), _dptr(out["hist"]), _dptr(ws), ws.numel(),
+                                 _stream(stream)), "mgs_quant_sweep")
+    _finish(ws, check, "mgs_quant_sweep", stream)
+    return out
+
+
+def quantize(attr, kept, G: int, bw, stream=None):
+    """Codes ``u16 [C][k]`` (returned as int16 storage) and ``gmin, gmax [C][ng]``."""
+    torch = _torch()
+    C, N = attr.shape
+    k = kept.numel()
+    ng = (k + G - 1) // G
+    dev = attr.device
+    codes = torch.empty((C, k), dtype=torch.int16, device=dev)
+    mn = torch.empty((C, ng), dtype=torch.float32, device=dev)
+    mx = torch.empty((C, ng), dtype=torch.float32, device=dev)
+    _check(lib().mgs_quantize(_dptr(attr), N, C, _dptr(kept), k, G, _dptr(bw), _dptr(codes), _dptr(mn),
+                              _dptr(mx), _stream(stream)), "mgs_quantize")
+    return codes, mn, mx
+
+
+def dequantize(codes, G: int, bw, gmin, gmax, stream=None):
+    torch = _torch()
+    C, k = codes.shape
+    out = torch.empty((C, k), dtype=torch.float32, device=codes.device)
+    _check(lib().mgs_dequantize(_dptr(codes), k, C, G, _dptr(bw), _dptr(gmin), _dptr(gmax), _dptr(out),
+                                _stream(stream)), "mgs_dequantize")
+    return out
+
+
+def vq_assign(x, cb, want_dist: bool = True, ws=None, stream=None, check: bool = True):
+    """Nearest codeword ``idx i32[N]``, its FP64 distance, and the fallback row count."""
+    torch = _torch()
+    N, D = x.shape
+    K = cb.shape[0]
+    dev = x.device
+    need = lib().mgs_vq_assign_ws_bytes(N, D, K)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    idx = torch.empty(N, dtype=torch.int32, device=dev)
+    dist = torch.empty(N, dtype=torch.float64, device=dev) if want_dist else None
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().mgs_vq_assign(_dptr(x), N, D, _dptr(cb), K, _dptr(idx) if N else None,
+                               _dptr(dist) if (dist is not None and N) else None, _dptr(nfb), _dptr(ws),
+                               ws.numel(), _stream(stream)), "mgs_vq_assign")
+    _finish(ws, check, "mgs_vq_assign", stream)
+    return idx, dist, nfb
+
+
+# ----------------------------------------------------------------- host side
+def ilp_solve(err: np.ndarray, size: np.ndarray, budget: int):
+    """Exact 0-1 ILP; ``(choice u8[ncls], obj, used)`` or None when infeasible."""
+    err = np.ascontiguousarray(err, dtype=np.float64)
+    size = np.ascontiguousarray(size, dtype=np.int64)
+    ncls, nopt = err.shape
+    choice = np.empty(ncls, dtype=np.uint8)
+    obj = ct.c_double(0.0)
+    used = ct.c_int64(0)
+    code = lib().mgs_ilp_solve(_np_ptr(err), _np_ptr(size), ncls, nopt, int(budget), _np_ptr(choice),
+                               ct.byref(obj), ct.byref(used))
+    if code == EINFEASIBLE:
+        return None
+    _check(code, "mgs_ilp_solve")
+    return choice, obj.value, used.value
+
+
+def size_table(bits_table: np.ndarray, n_per_group=None, bit_list=None, mode: int = 0):
+    bits_table = np.ascontiguousarray(bits_table, dtype=np.float64)
+    ncls, nb = bits_table.shape
+    out = np.empty((ncls, nb), dtype=np.int64)
+    n = np.ascontiguousarray(n_per_group if n_per_group is not None else np.zeros(ncls), dtype=np.int64)
+    bl = np.ascontiguousarray(bit_list if bit_list is not None else np.zeros(nb), dtype=np.uint8)
+    _check(lib().mgs_size_table(_np_ptr(bits_table), _np_ptr(n), ncls, nb, _np_ptr(bl), mode, _np_ptr(out)),
+           "mgs_size_table")
+    return out
+
+
+def search(N: int, C: int, k, G: int, bits, err: np.ndarray, bits_table: np.ndarray, budget_bits: int,
+           size_mode: int = 0, threads: int = 0):
+    """Reserve-ratio loop + exact ILP over host copies of a sweep's tables.
+
+    Returns dict(best_t, best_bits u8[C][ng], obj f64[T], used i64[T]); best_t is -1
+    when no ratio is admissible.
+    """
+    d = sweep_desc(N, C, k, G, bits)
+    err = np.ascontiguousarray(err, dtype=np.float64)
+    bt = np.ascontiguousarray(bits_table, dtype=np.float64)
+    T = d.T
+    kk = d._keep[0]
+    ngmax = (int(kk.max()) + G - 1) // G
+    best_t = ct.c_int32(-1)
+    best_bits = np.zeros(C * max(ngmax, 1), dtype=np.uint8)
+    obj = np.empty(T, dtype=np.float64)
+    used = np.empty(T, dtype=np.int64)
+    code = lib().mgs_search(ct.byref(d), _np_ptr(err), _np_ptr(bt), int(budget_bits), size_mode, threads,
+                            ct.byref(best_t), _np_ptr(best_bits), _np_ptr(obj), _np_ptr(used))
+    if code not in (OK, EINFEASIBLE):
+        _check(code, "mgs_search")
+    t = best_t.value
+    ng = (int(kk[t]) + G - 1) // G if t >= 0 else 0
+    return {"best_t": t, "best_bits": best_bits[:C * ng].reshape(C, ng) if t >= 0 else None,
+            "obj": obj, "used": used}

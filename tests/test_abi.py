@@ -1,0 +1,99 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects bad arguments before touching the device (runs without a GPU)."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_26799_amd import mgs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "mgs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mgs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    L = mgs.lib()
+    syms = header_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(mgs.SIGNATURES), "binding and header disagree"
+
+
+def test_strerror_and_version():
+    assert mgs.strerror(0) == "ok"
+    for code in (-1, -2, -3, -4, -5, -6):
+        assert mgs.strerror(code) not in ("ok", "unknown status")
+    assert b"gfx950" in mgs.lib().mgs_version()
+
+
+def test_sweep_rejects_bad_descriptors():
+    L = mgs.lib()
+    fake = ct.c_void_p(0x1000)  # never dereferenced: validation fails first
+    base = dict(N=100, C=2, k=[50, 100], G=16, bits=[2, 4])
+
+    def call(**kw):
+        a = dict(base)
+        a.update(kw)
+        d = mgs.sweep_desc(a["N"], a["C"], a["k"], a["G"], a["bits"])
+        if "ld" in kw:
+            d.ld = kw["ld"]
+        return L.mgs_quant_sweep(ct.byref(d), fake, fake, fake, fake, fake, fake, fake, None, None, 0, None)
+
+    assert call(G=0) == mgs.EINVAL
+    assert call(G=65536) == mgs.EINVAL
+    assert call(bits=[4, 2]) == mgs.EINVAL          # not increasing
+    assert call(bits=[2, 2]) == mgs.EINVAL          # duplicate
+    assert call(bits=[0, 3]) == mgs.EINVAL
+    assert call(bits=[3, 17]) == mgs.EINVAL
+    assert call(k=[101]) == mgs.EINVAL              # k > N
+    assert call(k=[-1]) == mgs.EINVAL
+    assert call(k=[1] * 65) == mgs.EINVAL           # too many ratios
+    assert call(ld=50) == mgs.EINVAL                # ld < N
+    assert call() == mgs.EWORKSPACE                 # valid, but no workspace
+    assert L.mgs_quant_sweep(None, fake, fake, fake, fake, fake, fake, fake, None, fake, 1 << 20,
+                             None) == mgs.EINVAL
+
+
+def test_other_entry_points_reject_bad_arguments():
+    L = mgs.lib()
+    fake = ct.c_void_p(0x1000)
+    k = np.array([5], np.int64)
+    kp = k.ctypes.data_as(ct.c_void_p)
+    assert L.mgs_prune_select(None, 10, kp, 1, fake, fake, 1 << 20, None) == mgs.EINVAL
+    assert L.mgs_prune_select(fake, 10, kp, 0, fake, fake, 1 << 20, None) == mgs.EINVAL
+    assert L.mgs_prune_select(fake, 4, kp, 1, fake, fake, 1 << 20, None) == mgs.EINVAL  # k > n
+    assert L.mgs_prune_select(fake, 10, kp, 1, fake, None, 0, None) == mgs.EWORKSPACE
+    assert L.mgs_quantize(fake, 10, 0, fake, 5, 4, fake, fake, fake, fake, None) == mgs.EINVAL
+    assert L.mgs_quantize(fake, 10, 2, fake, 5, 0, fake, fake, fake, fake, None) == mgs.EINVAL
+    assert L.mgs_quantize(fake, 10, 2, None, 5, 4, fake, fake, fake, fake, None) == mgs.EINVAL
+    assert L.mgs_dequantize(fake, 5, 2, 70000, fake, fake, fake, fake, None) == mgs.EINVAL
+    assert L.mgs_vq_assign(fake, 10, 0, fake, 4, fake, None, None, fake, 1 << 20, None) == mgs.EINVAL
+    assert L.mgs_vq_assign(fake, 10, 65, fake, 4, fake, None, None, fake, 1 << 20, None) == mgs.EINVAL
+    assert L.mgs_vq_assign(fake, 10, 36, fake, 0, fake, None, None, fake, 1 << 20, None) == mgs.EINVAL
+    assert L.mgs_vq_assign(fake, 10, 36, fake, 4, fake, None, None, None, 0, None) == mgs.EWORKSPACE
+    assert L.mgs_status_fetch(None, None) == mgs.EWORKSPACE
+
+
+def test_workspace_queries():
+    L = mgs.lib()
+    assert L.mgs_prune_select_ws_bytes(5_300_000, 32) > L.mgs_prune_select_ws_bytes(1000, 1) > 0
+    assert L.mgs_vq_assign_ws_bytes(3_000_000, 36, 4096) >= 3_000_000 * 4
+    assert L.mgs_vq_assign_ws_bytes(10, 0, 4) == 0
+    d = mgs.sweep_desc(1000, 11, [500, 1000], 4096, [4, 5, 6])
+    assert L.mgs_quant_sweep_ws_bytes(ct.byref(d)) >= 256 + 8 * 4097
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    """The product path has no fallback: a missing library is an error."""
+    monkeypatch.setattr(mgs, "_lib", None)
+    monkeypatch.setattr(mgs, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        mgs.lib()

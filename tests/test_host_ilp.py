@@ -1,0 +1,140 @@
+"""The library's host 0-1 ILP and reserve-ratio loop against the oracle (CPU)."""
+import numpy as np
+import pytest
+
+from paper_2604_26799_amd import mgs, synth
+
+
+def rand_table(rng, ncls, nopt, kind):
+    if kind == "mono":  # loss falls and size grows with the option, like bit-widths
+        err = np.sort(rng.lognormal(0, 2, (ncls, nopt)), axis=1)[:, ::-1].copy()
+        size = np.sort(rng.integers(5, 400, (ncls, nopt)), axis=1)
+    elif kind == "ties":
+        err = rng.integers(0, 5, (ncls, nopt)).astype(np.float64)
+        size = rng.integers(0, 6, (ncls, nopt)) * 10
+    else:
+        err = rng.uniform(0, 100, (ncls, nopt))
+        size = rng.integers(0, 60, (ncls, nopt))
+    return err, size
+
+
+def test_hand_case():
+    err = np.array([[4.0, 1.0], [3.0, 2.0]])
+    size = np.array([[10, 20], [10, 20]])
+    choice, obj, used = mgs.ilp_solve(err, size, 30)
+    assert choice.tolist() == [1, 0] and obj == 4.0 and used == 30
+    assert mgs.ilp_solve(err, size, 19) is None
+
+
+@pytest.mark.parametrize("kind", ["mono", "ties", "free"])
+def test_vs_exhaustive(orc, kind):
+    rng = np.random.default_rng({"mono": 1, "ties": 2, "free": 3}[kind])
+    for trial in range(150):
+        ncls = int(rng.integers(1, 7))
+        nopt = int(rng.integers(1, 6))
+        err, size = rand_table(rng, ncls, nopt, kind)
+        budget = int(rng.integers(0, max(1, size.sum(1).max() * ncls // 2 + 1)))
+        a = orc.ilp_exhaustive(err, size, budget)
+        b = mgs.ilp_solve(err, size, budget)
+        assert (a is None) == (b is None), (trial, budget)
+        if a is not None:
+            assert b[1] == a[1] and b[2] == a[2], (trial, a, b)
+            assert b[0].tolist() == a[0].tolist(), (trial, a, b)
+
+
+def test_vs_dp_medium(orc):
+    rng = np.random.default_rng(9)
+    for trial in range(25):
+        ncls = int(rng.integers(10, 60))
+        nopt = int(rng.integers(2, 16))
+        err, size = rand_table(rng, ncls, nopt, "mono" if trial % 2 else "free")
+        lo, hi = int(size.min(1).sum()), int(size.max(1).sum())
+        budget = int(rng.uniform(lo, hi))
+        a = orc.ilp_dp(err, size, budget)
+        b = mgs.ilp_solve(err, size, budget)
+        assert (a is None) == (b is None)
+        if a is not None:
+            assert b[1] == pytest.approx(a[1], rel=1e-12) and b[2] == a[2]
+            if b[0].tolist() != a[0].tolist():  # only possible on an exact tie
+                assert b[1] == a[1]
+
+
+def test_large_vs_highs():
+    """Thousands of classes (the size of a real sweep's table) against HiGHS."""
+    from scipy.optimize import LinearConstraint, milp
+    rng = np.random.default_rng(12)
+    ncls, nopt = 1500, 16
+    err, size = rand_table(rng, ncls, nopt, "mono")
+    budget = int(0.35 * size.min(1).sum() + 0.65 * size.max(1).sum())
+    choice, obj, used = mgs.ilp_solve(err, size, budget)
+    assert used <= budget
+    A_eq = np.kron(np.eye(ncls), np.ones(nopt))
+    res = milp(err.ravel(), constraints=[LinearConstraint(A_eq, 1, 1),
+                                         LinearConstraint(size.reshape(1, -1), 0, budget)],
+               integrality=np.ones(ncls * nopt), bounds=(0, 1),
+               options={"mip_rel_gap": 0, "time_limit": 120})
+    assert res.status == 0
+    assert obj <= res.fun * (1 + 1e-9)
+    assert obj == pytest.approx(res.fun, rel=1e-9)
+
+
+def test_budget_edges():
+    rng = np.random.default_rng(4)
+    err, size = rand_table(rng, 40, 8, "mono")
+    big = mgs.ilp_solve(err, size, int(size.max(1).sum()) + 5)
+    assert big[0].tolist() == list(np.argmin(err, axis=1))
+    tight = mgs.ilp_solve(err, size, int(size.min(1).sum()))
+    assert (size[np.arange(40), tight[0]] == size.min(1)).all()
+    assert mgs.ilp_solve(err, size, int(size.min(1).sum()) - 1) is None
+    with pytest.raises(mgs.MgsError):
+        bad = err.copy()
+        bad[3, 2] = np.nan
+        mgs.ilp_solve(bad, size, 1000)
+
+
+def test_size_table_modes(orc):
+    rng = np.random.default_rng(1)
+    bits = rng.uniform(0, 5000, (30, 5))
+    bits[3] = 0.0
+    bits[4, 1] = 17.0  # exact integer stays as is
+    n = rng.integers(1, 4096, 30)
+    bl = [2, 4, 5, 8, 16]
+    assert np.array_equal(mgs.size_table(bits, mode=0), orc.size_table(bits))
+    assert np.array_equal(mgs.size_table(bits, n, bl, mode=1), orc.size_table(bits, n, bl, "linear"))
+
+
+def test_search_vs_oracle(orc):
+    """Reserve-ratio loop + ILP on the oracle's tables of a small scene."""
+    w = synth.SweepWorkload("t", 6000, 11, synth.ratios_uniform(synth.Fraction(2, 10), synth.Fraction(9, 10), 5),
+                            512, [2, 4, 6, 8])
+    attr, imp = w.make()
+    k = w.k
+    kept = orc.prune_select(imp, k)
+    tab = orc.quant_sweep(attr, imp, kept, k, w.group, w.bits)
+    raw_bits = w.n * w.channels * 32
+    for ratio in (8, 12, 20, 40):
+        budget = raw_bits // ratio
+        res = mgs.search(w.n, w.channels, k, w.group, w.bits, tab["err"], tab["bits"], budget)
+        rows = []
+        for t in range(len(k)):
+            ng = (int(k[t]) + w.group - 1) // w.group
+            e = tab["err"][t, :, :ng].reshape(-1, len(w.bits))
+            s = orc.size_table(tab["bits"][t, :, :ng].reshape(-1, len(w.bits)))
+            size8 = int(s[:, w.bits.index(8)].sum())
+            sol = orc.ilp_dp(e, s, budget) if 2 * size8 >= budget else None
+            rows.append({"tau": int(k[t]), "size8": size8, "budget": budget,
+                         "obj": None if sol is None else sol[1], "sol": sol})
+            if 2 * size8 < budget:
+                assert np.isnan(res["obj"][t])
+            elif sol is None:
+                assert np.isnan(res["obj"][t])
+            else:
+                assert res["obj"][t] == pytest.approx(sol[1], rel=1e-12)
+                assert res["used"][t] == sol[2]
+        best = orc.choose_ratio(rows)
+        if best is None:
+            assert res["best_t"] == -1
+            continue
+        assert res["best_t"] == best
+        want = np.asarray(w.bits, np.uint8)[rows[best]["sol"][0]].reshape(w.channels, -1)
+        assert np.array_equal(res["best_bits"], want)
