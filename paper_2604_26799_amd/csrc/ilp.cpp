@@ -13,12 +13,15 @@
 //      hull increments by efficiency gives the Lagrange multiplier lambda of
 //      the size constraint, a lower bound L(lambda) and an integer
 //      incumbent (improved by single-class moves);
-//   3. reduced costs r = (err + lambda size) - min over the class: an option
-//      with r > incumbent - L(lambda) is in no solution at least as good as
-//      the incumbent, so it is removed; classes left with one option are
-//      fixed;
-//   4. dynamic programming over the remaining classes in index order on
-//      (size, loss) states with dominance pruning and the Lagrangian bound.
+//   3. reduced costs r = (err + lambda size) - min over the class: any
+//      solution costs at least L(lambda) + sum of its reduced costs, so an
+//      option with r > incumbent - L(lambda) is in no solution at least as
+//      good as the incumbent;
+//   4. expanding core: dynamic programming over (size, loss) states with
+//      dominance pruning and the Lagrangian bound, first over the classes
+//      whose alternatives are cheapest (beam-limited, to improve the
+//      incumbent and so shrink the gap), then exactly over every class that
+//      can still change; the others keep their Lagrangian-best option.
 // Among optimal solutions the smaller total size wins, then the smaller
 // option index in class order.
 #include <algorithm>
@@ -37,6 +40,7 @@ namespace {
 
 constexpr double kInf = std::numeric_limits<double>::infinity();
 constexpr size_t kStateCap = 20u * 1000u * 1000u;
+constexpr size_t kBeam = 20000;  // states per layer in the incumbent passes
 
 struct Opt {
     double e;
@@ -64,6 +68,89 @@ bool path_less(const std::vector<std::vector<State>>& layers, size_t layer, int3
     for (size_t i = pa.size(); i-- > 0;)
         if (pa[i] != pb[i]) return pa[i] < pb[i];
     return false;
+}
+
+// Dynamic programming over the classes of a core (in the given order) on
+// (size, loss) states: dominated states are dropped, states whose Lagrangian
+// bound exceeds UB are pruned, and with beam > 0 only the `beam` states of
+// best bound survive a layer (a heuristic pass).  Writes the option index of
+// every core class of the best final state (least loss, then least size,
+// then lexicographically smallest path).
+int core_dp(const std::vector<std::vector<Opt>>& opts, double e_fixed, int64_t cap, double lambda,
+            double UB, double tol, size_t beam, std::vector<int16_t>& pick) {
+    const size_t n = opts.size();
+    if (cap < 0) return MGS_EINFEASIBLE;
+    std::vector<double> mr(n + 1, 0.0);  // suffix sums of min(e + lambda s)
+    for (size_t i = n; i-- > 0;) {
+        double m = kInf;
+        for (const Opt& x : opts[i]) m = std::min(m, x.e + lambda * (double)x.s);
+        mr[i] = mr[i + 1] + m;
+    }
+    std::vector<std::vector<State>> layers;
+    std::vector<State> cur{{0, 0.0, -1, -1}};
+    std::vector<State> nxt;
+    size_t total_states = 1;
+    for (size_t li = 0; li < n; ++li) {
+        nxt.clear();
+        for (int32_t si = 0; si < (int32_t)cur.size(); ++si) {
+            const State& st = cur[si];
+            for (const Opt& x : opts[li]) {
+                int64_t w = st.w + x.s;
+                if (w > cap) continue;
+                double z = st.z + x.e;
+                double lb = e_fixed + z + mr[li + 1] - lambda * (double)(cap - w);
+                if (lb > UB + tol) continue;
+                nxt.push_back({w, z, si, (int16_t)x.j});
+            }
+        }
+        layers.push_back(cur);
+        std::sort(nxt.begin(), nxt.end(), [](const State& a, const State& b) {
+            if (a.w != b.w) return a.w < b.w;
+            return a.z < b.z;
+        });
+        cur.clear();
+        for (size_t i = 0; i < nxt.size(); ++i) {
+            const State& st = nxt[i];
+            if (!cur.empty()) {
+                State& last = cur.back();
+                if (st.z > last.z) continue;
+                if (st.z == last.z) {
+                    // same loss with more size is dominated; same (size, loss) keeps
+                    // the lexicographically smaller path: parents first, then option
+                    if (st.w == last.w) {
+                        bool less = st.prev == last.prev
+                                        ? st.opt < last.opt
+                                        : path_less(layers, layers.size() - 1, st.prev, last.prev);
+                        if (less) last = st;
+                    }
+                    continue;
+                }
+            }
+            cur.push_back(st);
+        }
+        if (beam && cur.size() > beam) {
+            std::nth_element(cur.begin(), cur.begin() + beam, cur.end(), [&](const State& a, const State& b) {
+                return a.z + lambda * (double)a.w < b.z + lambda * (double)b.w;
+            });
+            cur.resize(beam);
+        }
+        total_states += cur.size();
+        if (total_states > kStateCap) return MGS_ELIMIT;
+        if (cur.empty()) return MGS_EINFEASIBLE;
+    }
+    // least loss; among equal loss the dominance pass kept the least size
+    int32_t best = 0;
+    for (int32_t i = 1; i < (int32_t)cur.size(); ++i)
+        if (cur[i].z < cur[best].z || (cur[i].z == cur[best].z && cur[i].w < cur[best].w)) best = i;
+    pick.assign(n, 0);
+    layers.push_back(cur);
+    int32_t si = best;
+    for (size_t li = n; li-- > 0;) {
+        const State& st = layers[li + 1][si];
+        pick[li] = st.opt;
+        si = st.prev;
+    }
+    return MGS_OK;
 }
 
 int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_t budget,
@@ -179,106 +266,82 @@ int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_
     double UB = 0.0;
     for (int64_t c = 0; c < ncls; ++c) UB += cls[c][inc_pos[c]].e;
 
-    // ---- 3. Lagrangian bound and reduced-cost fixing
+    // ---- 3. Lagrangian bound, reduced costs, Lagrangian-best option per class
     std::vector<double> mlam(ncls);
+    std::vector<int> lagbest(ncls, 0);
     double LB0 = -lambda * (double)budget;
     double scale = std::fabs(UB);
     for (int64_t c = 0; c < ncls; ++c) {
         double m = kInf;
-        for (const Opt& x : cls[c]) m = std::min(m, x.e + lambda * (double)x.s);
+        for (int i = 0; i < (int)cls[c].size(); ++i) {
+            double v = cls[c][i].e + lambda * (double)cls[c][i].s;
+            if (v < m) {  // options are sorted by size: ties keep the smaller size
+                m = v;
+                lagbest[c] = i;
+            }
+        }
         mlam[c] = m;
         LB0 += m;
         scale = std::max(scale, std::fabs(m));
     }
     const double tol = 1e-9 * (scale + std::fabs(LB0) + std::fabs(lambda * (double)budget)) + 1e-300;
-    const double gap = UB - LB0 + tol;
-    std::vector<std::vector<Opt>> live(ncls);
-    std::vector<int64_t> core;
-    double e_fixed = 0.0;
-    int64_t s_fixed = 0;
-    for (int64_t c = 0; c < ncls; ++c) {
-        for (const Opt& x : cls[c])
-            if (x.e + lambda * (double)x.s - mlam[c] <= gap) live[c].push_back(x);
-        if (live[c].empty()) live[c].push_back(cls[c][inc_pos[c]]);  // numerical safety
-        if (live[c].size() == 1) {
-            e_fixed += live[c][0].e;
-            s_fixed += live[c][0].s;
-        } else {
-            core.push_back(c);
-        }
-    }
-    // ---- 4. DP over the core classes (index order)
-    const int64_t cap_core = budget - s_fixed;
-    if (cap_core < 0) return MGS_EINFEASIBLE;  // (cannot happen: incumbent is feasible)
-    // M_R suffix sums of the Lagrangian minima of the remaining core classes
-    std::vector<double> mr(core.size() + 1, 0.0);
-    for (size_t i = core.size(); i-- > 0;) {
-        double m = kInf;
-        for (const Opt& x : live[core[i]]) m = std::min(m, x.e + lambda * (double)x.s);
-        mr[i] = mr[i + 1] + m;
-    }
-    std::vector<std::vector<State>> layers;
-    std::vector<State> cur{{0, 0.0, -1, -1}};
-    std::vector<State> nxt;
-    size_t total_states = 1;
-    for (size_t li = 0; li < core.size(); ++li) {
-        const int64_t c = core[li];
-        nxt.clear();
-        for (int32_t si = 0; si < (int32_t)cur.size(); ++si) {
-            const State& st = cur[si];
-            for (const Opt& x : live[c]) {
-                int64_t w = st.w + x.s;
-                if (w > cap_core) continue;
-                double z = st.z + x.e;
-                // Lagrangian bound over the classes after this one
-                double lb = e_fixed + z + mr[li + 1] - lambda * (double)(cap_core - w);
-                if (lb > UB + tol) continue;
-                nxt.push_back({w, z, si, (int16_t)x.j});
-            }
-        }
-        layers.push_back(cur);
-        // dominance: sort by size, keep strictly improving loss
-        std::sort(nxt.begin(), nxt.end(), [](const State& a, const State& b) {
-            if (a.w != b.w) return a.w < b.w;
-            return a.z < b.z;
-        });
-        cur.clear();
-        for (size_t i = 0; i < nxt.size(); ++i) {
-            const State& st = nxt[i];
-            if (!cur.empty()) {
-                State& last = cur.back();
-                if (st.z > last.z) continue;
-                if (st.z == last.z) {
-                    // same loss with more size is dominated; same (size, loss) keeps
-                    // the lexicographically smaller path: parents first, then option
-                    if (st.w == last.w) {
-                        bool less = st.prev == last.prev
-                                        ? st.opt < last.opt
-                                        : path_less(layers, layers.size() - 1, st.prev, last.prev);
-                        if (less) last = st;
-                    }
-                    continue;
-                }
-            }
-            cur.push_back(st);
-        }
-        total_states += cur.size();
-        if (total_states > kStateCap) return MGS_ELIMIT;
-    }
-    // best final state: minimal loss, then minimal size (cur is sorted by size
-    // with strictly decreasing loss, so the last state has the minimal loss)
-    if (cur.empty()) return MGS_EINFEASIBLE;
-    int32_t best = (int32_t)cur.size() - 1;
-    // fixed classes' choices
+    // smallest reduced cost of any other option of the class
+    std::vector<double> rcmin(ncls, kInf);
     for (int64_t c = 0; c < ncls; ++c)
-        if (live[c].size() == 1) choice[c] = (uint8_t)live[c][0].j;
-    // core choices by walking back
-    int32_t si = best;
-    layers.push_back(cur);
-    for (size_t li = core.size(); li-- > 0;) {
-        const State& st = layers[li + 1][si];
-        choice[core[li]] = (uint8_t)st.opt;
-        si = st.prev;
+        for (int i = 0; i < (int)cls[c].size(); ++i)
+            if (i != lagbest[c])
+                rcmin[c] = std::min(rcmin[c], cls[c][i].e + lambda * (double)cls[c][i].s - mlam[c]);
+    std::vector<int64_t> order(ncls);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return rcmin[a] < rcmin[b]; });
+
+    // ---- 4. expanding core: DP over the classes whose alternatives are
+    // cheapest in reduced cost improves the incumbent, which shrinks the gap;
+    // once every class that can still change (rcmin <= gap) fits in the core,
+    // one exact DP over exactly those classes finishes.
+    size_t K = 32;
+    for (;;) {
+        const double gap = UB - LB0 + tol;
+        std::vector<int64_t> need;
+        for (int64_t c : order) {
+            if (rcmin[c] > gap) break;
+            need.push_back(c);
+        }
+        const bool final_pass = need.size() <= K;
+        std::vector<int64_t> core = final_pass ? need : std::vector<int64_t>(order.begin(), order.begin() + K);
+        if (final_pass) std::sort(core.begin(), core.end());  // index order for the tie rule
+        std::vector<char> in_core(ncls, 0);
+        for (int64_t c : core) in_core[c] = 1;
+        double e_fixed = 0.0;
+        int64_t s_fixed = 0;
+        for (int64_t c = 0; c < ncls; ++c)
+            if (!in_core[c]) {
+                e_fixed += cls[c][lagbest[c]].e;
+                s_fixed += cls[c][lagbest[c]].s;
+            }
+        std::vector<std::vector<Opt>> opts(core.size());
+        for (size_t i = 0; i < core.size(); ++i)
+            for (const Opt& x : cls[core[i]])
+                if (x.e + lambda * (double)x.s - mlam[core[i]] <= gap) opts[i].push_back(x);
+        std::vector<int16_t> pick;
+        double zb = 0.0;
+        int rc = core_dp(opts, e_fixed, budget - s_fixed, lambda, UB, tol,
+                         final_pass ? 0 : kBeam, pick);
+        if (rc == MGS_ELIMIT) return rc;
+        if (final_pass) {
+            if (rc != MGS_OK) return MGS_EINFEASIBLE;  // (cannot happen: the incumbent is a state)
+            for (int64_t c = 0; c < ncls; ++c)
+                if (!in_core[c]) choice[c] = (uint8_t)cls[c][lagbest[c]].j;
+            for (size_t i = 0; i < core.size(); ++i) choice[core[i]] = (uint8_t)pick[i];
+            break;
+        }
+        if (rc == MGS_OK) {
+            zb = e_fixed;
+            for (size_t i = 0; i < core.size(); ++i) zb += err[core[i] * nopt + pick[i]];
+            if (zb < UB) UB = zb;
+        }
+        K *= 4;
     }
     double o = 0.0;
     int64_t u = 0;

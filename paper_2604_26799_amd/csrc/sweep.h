@@ -83,12 +83,15 @@ bool shape_valid(const Shape& sh, int G);
 // tables (NaN padding, status reset, debug histogram clearing).
 int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
                 mgs_status_block* status, double* lgtab, int lgtab_max, hipStream_t s);
+// G: the largest group size of the launch (selects the chunked kernel when
+// it exceeds the shape's nt * ept).
 int launch_sweep(const SweepParams& p, const TileRef* tiles, const Shape& sh, size_t lds,
-                 int64_t grid, hipStream_t s);
-int max_resident_blocks(const Shape& sh, size_t lds);
+                 int64_t grid, hipStream_t s, int G);
+int max_resident_blocks(const Shape& sh, size_t lds, int G);
 int device_cus();
 int variant_count();
 Shape variant_shape(int i);
+bool variant_chunked(int i);
 
 // Autotune registry: the shape chosen for (G, nb, bmax), if any.
 bool tuned_shape(int G, int nb, int bmax, Shape* out);

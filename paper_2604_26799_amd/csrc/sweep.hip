@@ -146,7 +146,7 @@ __device__ __forceinline__ double eval_fast_dispatch(bool check, bool err, const
     return eval_fast<NT, EPT, XT, PACKED, false, false>(u, xd, wd, n, tid, P, S, Z, hist, base);
 }
 
-template <int NT, int EPT>
+template <int NT, int EPT, bool CHUNKED>
 __global__ __launch_bounds__(NT) void sweep_kernel(SweepParams p, const TileRef* __restrict__ tiles) {
     constexpr int NW = NT / MGS_WAVE;
     // per-element copies: FP64 when registers allow, else FP32 converted per use
@@ -192,27 +192,38 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepParams p, const TileRef*
         const float* row = sc->attr + (int64_t)c * sc->ld;
         const int64_t slot = ((int64_t)t * sc->C + c) * sc->gmaxn + g;
         const int nb = sc->nb;
-        const bool check = n < NT * EPT;
 
-        // ---- gather values and weights, min / max, finiteness
+        // ---- gather values and weights, min / max, finiteness.  A group
+        // larger than the block's register capacity (NT * EPT) is processed
+        // in chunks that are gathered again for every histogram batch.
+        constexpr int CAP = NT * EPT;
+        // (the non-chunked instantiation is only launched when G <= CAP)
+        const int nchunk = CHUNKED ? (n + CAP - 1) / CAP : 1;
         float u[EPT];
         XT xd[EPT], wd[EPT];
         float mn = INFINITY, mx = -INFINITY;
         uint32_t bad = 0;
+        auto gather = [&](int ch) {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            int j = i * NT + tid;
-            float x = 0.0f, w = 0.0f;
-            if (j < n) {
-                int32_t idx = J[j];
-                x = row[idx];
-                w = sc->imp[idx];
-                bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
-                mn = fminf(mn, x);
-                mx = fmaxf(mx, x);
+            for (int i = 0; i < EPT; ++i) {
+                int j = ch * CAP + i * NT + tid;
+                float x = 0.0f, w = 0.0f;
+                if (j < n) {
+                    int32_t idx = J[j];
+                    x = row[idx];
+                    w = sc->imp[idx];
+                    bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
+                    mn = fminf(mn, x);
+                    mx = fmaxf(mx, x);
+                }
+                xd[i] = (XT)x;
+                wd[i] = (XT)w;
             }
-            xd[i] = (XT)x;
-            wd[i] = (XT)w;
+        };
+        if constexpr (CHUNKED) {
+            for (int ch = nchunk - 1; ch >= 0; --ch) gather(ch);  // ends holding chunk 0
+        } else {
+            gather(0);
         }
         mn = wave_min_f32(mn);
         mx = wave_max_f32(mx);
@@ -265,13 +276,12 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepParams p, const TileRef*
         }
         for (int i = tid; i < MGS_MAX_BITS * NW; i += NT) (&bitpart[0][0])[i] = 0.0;
         const bool fast = R >= ldexpf(1.0f, sc->bmax - 126);
-        if (fast) {
+        auto quotients = [&]() {
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) u[i] = (float)xd[i] / R;
-        } else {
-#pragma unroll
-            for (int i = 0; i < EPT; ++i) u[i] = 0.0f;
-        }
+            for (int i = 0; i < EPT; ++i) u[i] = fast ? (float)xd[i] / R : 0.0f;
+        };
+        quotients();
+        for (int i = tid; i < MGS_MAX_BITS * NW; i += NT) (&errpart[0][0])[i] = 0.0;
         __syncthreads();
 
         // ---- histogram batches
@@ -280,40 +290,50 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepParams p, const TileRef*
             const int words = p.batch_words[bt];
             for (int w = tid; w < words; w += NT) hist[w] = 0u;
             __syncthreads();
-            for (int e = e0; e < e1; ++e) {
-                const HistEntry en = p.entries[e];
-                const int bi = en.bi;
-                const float S = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmS[bi])));
-                const float Z = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmZ[bi])));
-                const float P = ldexpf(1.0f, sc->bl[bi]);
-                const int base = en.lds_off - en.lo;
-                double acc = 0.0;
-                if (S == 0.0f) {
-                    // the range underflows at this b: every code is 0, xhat = min
-                    if (en.lo == 0 && tid == 0) hist[en.lds_off] += (uint32_t)n;
-                    if (en.first) {
+            for (int ch = 0; ch < nchunk; ++ch) {
+                if constexpr (CHUNKED) {
+                    if (nchunk > 1) {
+                        gather(ch);
+                        quotients();
+                    }
+                }
+                const int nc = min(CAP, n - ch * CAP);  // elements of this chunk
+                const bool check = nc < CAP;
+                for (int e = e0; e < e1; ++e) {
+                    const HistEntry en = p.entries[e];
+                    const int bi = en.bi;
+                    const float S = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmS[bi])));
+                    const float Z = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmZ[bi])));
+                    const float P = ldexpf(1.0f, sc->bl[bi]);
+                    const int base = en.lds_off - en.lo;
+                    double acc = 0.0;
+                    if (S == 0.0f) {
+                        // the range underflows at this b: every code is 0, xhat = min
+                        if (en.lo == 0 && tid == 0) hist[en.lds_off] += (uint32_t)nc;
+                        if (en.first) {
 #pragma unroll
-                        for (int i = 0; i < EPT; ++i) {
-                            if (i * NT + tid < n) {
-                                double d = (double)mn - as_f64(xd[i]);
-                                acc = __builtin_fma(as_f64(wd[i]), d * d, acc);
+                            for (int i = 0; i < EPT; ++i) {
+                                if (i * NT + tid < nc) {
+                                    double d = (double)mn - as_f64(xd[i]);
+                                    acc = __builtin_fma(as_f64(wd[i]), d * d, acc);
+                                }
                             }
                         }
+                    } else if (fast && !en.split && fabsf(Z) <= 8388608.0f) {
+                        if (en.packed)
+                            acc = eval_fast_dispatch<NT, EPT, XT, true>(check, en.first, u, xd, wd, nc, tid,
+                                                                    P, S, Z, hist, base);
+                        else
+                            acc = eval_fast_dispatch<NT, EPT, XT, false>(check, en.first, u, xd, wd, nc, tid,
+                                                                     P, S, Z, hist, base);
+                    } else {
+                        acc = eval_generic<NT, EPT, XT>(u, xd, wd, nc, tid, P, S, Z, hist, base, en.lo,
+                                                    en.nwords, en.packed, !fast, en.first);
                     }
-                } else if (fast && !en.split && fabsf(Z) <= 8388608.0f) {
-                    if (en.packed)
-                        acc = eval_fast_dispatch<NT, EPT, XT, true>(check, en.first, u, xd, wd, n, tid,
-                                                                P, S, Z, hist, base);
-                    else
-                        acc = eval_fast_dispatch<NT, EPT, XT, false>(check, en.first, u, xd, wd, n, tid,
-                                                                 P, S, Z, hist, base);
-                } else {
-                    acc = eval_generic<NT, EPT, XT>(u, xd, wd, n, tid, P, S, Z, hist, base, en.lo,
-                                                en.nwords, en.packed, !fast, en.first);
-                }
-                if (en.first) {
-                    acc = wave_sum_f64(acc);
-                    if (lane == 0) errpart[bi][wave] = acc;
+                    if (en.first) {
+                        acc = wave_sum_f64(acc);
+                        if (lane == 0) errpart[bi][wave] += acc;
+                    }
                 }
             }
             __syncthreads();
@@ -396,40 +416,50 @@ __global__ void sweep_init_kernel(const SceneDesc* __restrict__ scenes, int coun
 
 // ------------------------------------------------------------------ host side
 
-template <int NT, int EPT>
+template <int NT, int EPT, bool CHUNKED>
 static hipError_t launch_one(const SweepParams& p, const TileRef* tiles, int64_t grid, size_t lds,
                              hipStream_t s) {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel<NT, EPT>,
+        hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel<NT, EPT, CHUNKED>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)e;
     }
-    hipLaunchKernelGGL((sweep_kernel<NT, EPT>), dim3((unsigned)grid), dim3(NT), lds, s, p, tiles);
+    hipLaunchKernelGGL((sweep_kernel<NT, EPT, CHUNKED>), dim3((unsigned)grid), dim3(NT), lds, s, p,
+                       tiles);
     return hipGetLastError();
 }
 
 struct Variant {
     int nt, ept;
+    bool chunked;
     hipError_t (*fn)(const SweepParams&, const TileRef*, int64_t, size_t, hipStream_t);
     const void* kern;
 };
 
-#define MGS_V(NT, EPT) {NT, EPT, &launch_one<NT, EPT>, (const void*)&sweep_kernel<NT, EPT>}
+#define MGS_V(NT, EPT) \
+    {NT, EPT, false, &launch_one<NT, EPT, false>, (const void*)&sweep_kernel<NT, EPT, false>}
+#define MGS_VC(NT, EPT) \
+    {NT, EPT, true, &launch_one<NT, EPT, true>, (const void*)&sweep_kernel<NT, EPT, true>}
 static const Variant kVariants[] = {
     MGS_V(256, 1),  MGS_V(256, 2),  MGS_V(256, 4),  MGS_V(256, 8),  MGS_V(256, 16), MGS_V(256, 32),
     MGS_V(512, 1),  MGS_V(512, 2),  MGS_V(512, 4),  MGS_V(512, 8),  MGS_V(512, 16), MGS_V(512, 32),
     MGS_V(1024, 1), MGS_V(1024, 2), MGS_V(1024, 4), MGS_V(1024, 8), MGS_V(1024, 16),
+    MGS_VC(1024, 4),  // groups larger than any register-resident shape
 };
 #undef MGS_V
+#undef MGS_VC
 
-static const Variant* find_variant(int nt, int ept) {
+// A non-chunked variant when nt * ept covers the group, else the chunked one.
+static const Variant* find_variant(int nt, int ept, int G = 0) {
+    const bool need_chunk = (int64_t)nt * ept < G;
     for (const Variant& v : kVariants)
-        if (v.nt == nt && v.ept == ept) return &v;
+        if (v.nt == nt && v.ept == ept && v.chunked == need_chunk) return &v;
     return nullptr;
 }
 
 int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 Shape variant_shape(int i) { return Shape{kVariants[i].nt, kVariants[i].ept, 0}; }
+bool variant_chunked(int i) { return kVariants[i].chunked; }
 
 static int device_attr(hipDeviceAttribute_t a, int fallback) {
     int dev = 0, v = 0;
@@ -587,26 +617,25 @@ int fill_scene(const mgs_sweep_desc* d, const float* attr, const float* imp, con
     return MGS_OK;
 }
 
-bool shape_valid(const Shape& sh, int G) {
-    return find_variant(sh.nt, sh.ept) != nullptr && (int64_t)sh.nt * sh.ept >= G;
-}
+bool shape_valid(const Shape& sh, int G) { return find_variant(sh.nt, sh.ept, G) != nullptr; }
 
 // Default launch shape: the fewest elements per thread that still gives each
-// thread >= 8 of them (or the largest workgroup when G is small).
+// thread >= 8 of them (or the largest workgroup when G is small); groups
+// beyond 1024 x 16 elements are processed in chunks of that size.
 Shape default_shape(int G, int nb, int bmax) {
     (void)nb;
     (void)bmax;
     for (int e : {8, 16, 4, 2, 1, 32}) {
         for (int t : {256, 512, 1024}) {
-            if ((int64_t)t * e >= G && find_variant(t, e)) return Shape{t, e, 0};
+            if ((int64_t)t * e >= G && find_variant(t, e, G)) return Shape{t, e, 0};
         }
     }
-    return Shape{0, 0, 0};
+    return Shape{1024, 4, 0};  // chunked
 }
 
 int launch_sweep(const SweepParams& p, const TileRef* tiles, const Shape& sh, size_t lds,
-                 int64_t grid, hipStream_t s) {
-    const Variant* v = find_variant(sh.nt, sh.ept);
+                 int64_t grid, hipStream_t s, int G) {
+    const Variant* v = find_variant(sh.nt, sh.ept, G);
     if (!v) return MGS_EINVAL;
     if (grid <= 0 || grid > p.ntiles) grid = p.ntiles;
     if (grid < 1) return MGS_OK;
@@ -629,8 +658,8 @@ int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
     return mgs_last_launch();
 }
 
-int max_resident_blocks(const Shape& sh, size_t lds) {
-    const Variant* v = find_variant(sh.nt, sh.ept);
+int max_resident_blocks(const Shape& sh, size_t lds, int G) {
+    const Variant* v = find_variant(sh.nt, sh.ept, G);
     if (!v) return 1;
     int nblk = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, v->kern, sh.nt, lds) != hipSuccess ||
@@ -713,5 +742,5 @@ extern "C" int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, 
     p.lgtab_max = sc.G;
     p.ntiles = (int64_t)sc.C * sc.gpc;
     if (p.ntiles == 0) return MGS_OK;
-    return launch_sweep(p, nullptr, sh, lds, 0, s);
+    return launch_sweep(p, nullptr, sh, lds, 0, s, sc.G);
 }

@@ -19,7 +19,8 @@
 //      order).  The exact winner then satisfies s~_j <= min s~ + 2 E_i; a
 //      small FP64 slack 2 delta_i also admits the winner of the FP64
 //      definition when exact distances tie within FP64 rounding.
-//   3. Each lane keeps up to 8 candidates (s~ <= its running min + T_i);
+//   3. Each lane keeps up to 12 candidates (s~ <= the row's running min +
+//      T_i, the minimum shared between the row's two lanes every tile);
 //      at the end the row's candidates under the final threshold are
 //      re-scored with the FP64 definition (same operation order) and the
 //      smallest (distance, index) wins.  Rows whose buffer overflowed go to
@@ -42,7 +43,7 @@ constexpr int VQ_THREADS = VQ_WAVES * MGS_WAVE;
 constexpr int VQ_ROWSETS = 2;                          // 32-row sets per wave
 constexpr int VQ_ROWS = VQ_WAVES * VQ_ROWSETS * 32;    // rows per workgroup
 constexpr int VQ_CHUNK = 256;                          // codewords per LDS chunk
-constexpr int VQ_CAND = 8;                             // candidate slots per lane and row set
+constexpr int VQ_CAND = 12;                            // candidate slots per lane and row set
 constexpr int VQ_KS_MAX = 5;                           // 16-wide K steps (D + 2 <= 80)
 
 struct VqArgs {
@@ -155,12 +156,12 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
     }
     if (bad) atomicOr(&a.status->nonfinite, 1u);
 
-    float mhalf[VQ_ROWSETS];
+    float mrow[VQ_ROWSETS];
     int cnt[VQ_ROWSETS];
     int ovf[VQ_ROWSETS];
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-        mhalf[rs] = INFINITY;
+        mrow[rs] = INFINITY;
         cnt[rs] = 0;
         ovf[rs] = 0;
     }
@@ -190,8 +191,10 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
                 float tmin = acc[0];
 #pragma unroll
                 for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[i]);
-                mhalf[rs] = fminf(mhalf[rs], tmin);
-                const float thr = mhalf[rs] + T[rs];
+                // running minimum of the whole row: the partner lane holds the
+                // other 16 codewords of this tile
+                mrow[rs] = fminf(mrow[rs], fminf(tmin, __shfl_xor(tmin, 32, MGS_WAVE)));
+                const float thr = mrow[rs] + T[rs];
                 if (tmin <= thr && !ovf[rs]) {
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
@@ -228,8 +231,7 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
         const int64_t r = rows[rs];
-        const float mrow = fminf(mhalf[rs], __shfl_xor(mhalf[rs], 32, MGS_WAVE));
-        const float thr = mrow + T[rs];
+        const float thr = mrow[rs] + T[rs];
         const int ovf_row = ovf[rs] | __shfl_xor(ovf[rs], 32, MGS_WAVE);
         double best = INFINITY;
         int32_t bj = 0x7fffffff;

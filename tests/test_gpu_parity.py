@@ -179,9 +179,10 @@ def test_sweep_medium_workload_sampled(torch, orc):
     e = got["err"]
     ok = ~np.isnan(e[..., 0])
     assert (e[ok][:, 1:] <= e[ok][:, :-1] * (1 + 1e-6)).all()
-    n_per = np.minimum(w.group, k[:, None, None] - np.arange(e.shape[2])[None, None, :] * w.group)
-    bmax = got["bits"][ok].max(axis=1)
-    assert (bmax <= 16 * np.broadcast_to(n_per[:, None, :], e.shape[:3])[ok] + 1e-6).all()
+    n_per = np.minimum(w.group, k[:, None] - np.arange(e.shape[2])[None, :] * w.group)  # [T][Gmax]
+    n_all = np.broadcast_to(n_per[:, None, :], e.shape[:3])[ok]
+    assert (got["bits"][ok] <= np.asarray(w.bits)[None, :] * n_all[:, None] * (1 + 1e-12) + 1e-6).all()
+    assert (got["bits"][ok] <= np.log2(n_all)[:, None] * n_all[:, None] * (1 + 1e-12) + 1e-6).all()
 
 
 # ------------------------------------------------------------------ pruning
@@ -297,4 +298,4 @@ def test_vq_workload_sampled(torch, orc):
     np.testing.assert_array_equal(gi[rows], want_i)
     np.testing.assert_array_equal(gd[rows], want_d)
     assert (gi >= 0).all() and (gi < 4096).all()
-    assert int(host(nfb)[0]) < x.shape[0] // 100
+    assert int(host(nfb)[0]) < x.shape[0] // 1000  # exact full scans stay rare
