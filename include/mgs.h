@@ -173,15 +173,26 @@ int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float* d_cb, int
  * linear estimator P*Q of equation "size_estim").
  *
  * mgs_search: the reserve-ratio loop of the search algorithm over one
- * sweep's tables (host copies, layout of mgs_quant_sweep): for each ratio t
- * build the ILP over its C * ceil(k_t / G) groups, skip t when twice the
- * all-8-bit size is below the budget, solve, and choose the ratio with the
- * smallest loss (ties: larger t).  Writes h_best_t, the chosen bit-widths
- * h_best_bits[C][ceil(k_best / G)] (caller sizes it for the largest k),
- * and per ratio h_obj[t] (NaN when skipped or infeasible) and h_used[t].
- * Ratios are solved on up to `threads` host threads (0 = all cores).
- * Returns MGS_EINFEASIBLE when no ratio is admissible.
+ * sweep's tables (host copies, layout of mgs_quant_sweep; paper: Algorithm 1
+ * "Hyperparameter Optimization" and the discrete sampling of tau): for each
+ * ratio t build the ILP over its C * ceil(k_t / G) groups (class order:
+ * channel-major, then group), skip t when twice the all-8-bit size is below
+ * the budget, solve, and choose the ratio with the smallest loss (ties:
+ * larger k_t).  Ratios are solved in increasing order of their LP lower
+ * bound and a ratio whose bound exceeds the best optimum found is not solved
+ * (it cannot win); flags & MGS_SEARCH_ALL solves every admissible ratio.
+ * Writes h_best_t, the chosen bit-widths h_best_bits[C][ceil(k_best / G)]
+ * (caller sizes it for the largest k), per ratio h_obj[t] / h_used[t] (NaN / 0
+ * unless solved) and, if h_status is not NULL, h_status[t] (MGS_SEARCH_*).
+ * Host work runs on up to `threads` threads (0 = all cores).  Returns
+ * MGS_EINFEASIBLE when no ratio is admissible.
  * ====================================================================== */
+#define MGS_SEARCH_ALL 1            /* flags: solve every admissible ratio */
+#define MGS_SEARCH_SOLVED 0         /* h_status values */
+#define MGS_SEARCH_SKIPPED 1        /* doubled 8-bit size below the budget (or no groups) */
+#define MGS_SEARCH_INFEASIBLE 2     /* even the smallest allocation exceeds the budget */
+#define MGS_SEARCH_PRUNED 3         /* LP lower bound above the best optimum: not solved */
+
 int mgs_ilp_solve(const double* h_err, const int64_t* h_size, int64_t ncls, int32_t nopt,
                   int64_t budget, uint8_t* h_choice, double* h_obj, int64_t* h_used);
 
@@ -189,8 +200,9 @@ int mgs_size_table(const double* h_bits, const int64_t* h_n, int64_t ncls, int32
                    const uint8_t* h_bitlist, int32_t mode, int64_t* h_size);
 
 int mgs_search(const mgs_sweep_desc* desc, const double* h_err, const double* h_bits,
-               int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t* h_best_t,
-               uint8_t* h_best_bits, double* h_obj, int64_t* h_used);
+               int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t flags,
+               int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
+               int32_t* h_status);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,7 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <numeric>
 #include <vector>
 
@@ -40,7 +41,7 @@ namespace {
 
 constexpr double kInf = std::numeric_limits<double>::infinity();
 constexpr size_t kStateCap = 20u * 1000u * 1000u;
-constexpr size_t kBeam = 20000;  // states per layer in the incumbent passes
+constexpr size_t kBeam = 4000;  // states per layer in the incumbent passes
 
 struct Opt {
     double e;
@@ -70,70 +71,231 @@ bool path_less(const std::vector<std::vector<State>>& layers, size_t layer, int3
     return false;
 }
 
+// Lower bound on the cost of completing a partial solution from the classes
+// not yet processed, as a function of D = the capacity left if those classes
+// keep their Lagrangian-best options.  Relative to that default each class
+// offers points (dS, r) with r >= 0 the reduced cost; the LP relaxation takes
+// segments of each class's lower convex hull in order of cost per bit:
+//   D >= 0: h(D) = lambda D - savings of the upgrades cheaper than lambda per
+//           bit that fit into D (capacity left unused costs lambda per bit);
+//   D <  0: h(D) = cost of the cheapest downgrades freeing -D bits (infinite
+//           when they cannot).
+// h >= 0, so the Lagrangian bound plus h(D) is still a valid lower bound.
+struct Completion {
+    struct Seg {
+        double slope;  // reduced cost per bit
+        int64_t len;   // bits
+        int32_t cls;   // core position
+    };
+    std::vector<Seg> up, down;        // all segments, sorted by slope
+    std::vector<int64_t> ulen, dlen;  // cumulative lengths of the live ones
+    std::vector<double> usave, dcost, uslope, dslope;
+    double lambda = 0.0;
+
+    void build(const std::vector<std::vector<Opt>>& opts, const std::vector<double>& m,
+               const std::vector<int64_t>& sdef, double lam) {
+        lambda = lam;
+        for (size_t i = 0; i < opts.size(); ++i) {
+            std::vector<std::pair<int64_t, double>> pu, pd;  // (bits, r) away from the default
+            for (const Opt& x : opts[i]) {
+                const int64_t ds = x.s - sdef[i];
+                const double r = std::max(0.0, x.e + lam * (double)x.s - m[i]);
+                if (ds > 0) pu.push_back({ds, r});
+                if (ds < 0) pd.push_back({-ds, r});
+            }
+            add_hull(pu, (int32_t)i, up);
+            add_hull(pd, (int32_t)i, down);
+        }
+        auto by = [](const Seg& a, const Seg& b) { return a.slope < b.slope; };
+        std::stable_sort(up.begin(), up.end(), by);
+        std::stable_sort(down.begin(), down.end(), by);
+    }
+    // lower convex hull from (0, 0) of points (bits > 0, r)
+    static void add_hull(std::vector<std::pair<int64_t, double>>& pts, int32_t cls, std::vector<Seg>& out) {
+        if (pts.empty()) return;
+        std::sort(pts.begin(), pts.end());
+        std::vector<std::pair<int64_t, double>> h{{0, 0.0}};
+        for (const auto& q : pts) {
+            while (h.size() >= 2) {
+                const auto& a = h[h.size() - 2];
+                const auto& b = h.back();
+                if ((b.second - a.second) * (double)(q.first - a.first) >=
+                    (q.second - a.second) * (double)(b.first - a.first))
+                    h.pop_back();
+                else
+                    break;
+            }
+            if (q.first == h.back().first) {
+                if (q.second < h.back().second) h.back() = q;
+                continue;
+            }
+            h.push_back(q);
+        }
+        for (size_t k = 1; k < h.size(); ++k) {
+            int64_t len = h[k].first - h[k - 1].first;
+            out.push_back({(h[k].second - h[k - 1].second) / (double)len, len, cls});
+        }
+    }
+    // keep the segments of classes after position `done`
+    void restrict_after(int64_t done) {
+        ulen.clear(); usave.clear(); uslope.clear();
+        dlen.clear(); dcost.clear(); dslope.clear();
+        int64_t L = 0;
+        double V = 0.0;
+        for (const Seg& g : up) {
+            if (g.cls <= done || g.slope >= lambda) continue;
+            L += g.len;
+            V += (lambda - g.slope) * (double)g.len;
+            ulen.push_back(L); usave.push_back(V); uslope.push_back(g.slope);
+        }
+        L = 0;
+        V = 0.0;
+        for (const Seg& g : down) {
+            if (g.cls <= done) continue;
+            L += g.len;
+            V += g.slope * (double)g.len;
+            dlen.push_back(L); dcost.push_back(V); dslope.push_back(g.slope);
+        }
+    }
+    double h(int64_t D) const {
+        if (D >= 0) {
+            size_t k = std::lower_bound(ulen.begin(), ulen.end(), D) - ulen.begin();
+            if (k == ulen.size()) return std::max(0.0, lambda * (double)D - (usave.empty() ? 0.0 : usave.back()));
+            double prevL = k ? (double)ulen[k - 1] : 0.0, prevV = k ? usave[k - 1] : 0.0;
+            return std::max(0.0, lambda * (double)D - prevV - (lambda - uslope[k]) * ((double)D - prevL));
+        }
+        const int64_t F = -D;
+        size_t k = std::lower_bound(dlen.begin(), dlen.end(), F) - dlen.begin();
+        if (k == dlen.size()) return kInf;
+        double prevL = k ? (double)dlen[k - 1] : 0.0, prevV = k ? dcost[k - 1] : 0.0;
+        return prevV + dslope[k] * ((double)F - prevL);
+    }
+};
+
 // Dynamic programming over the classes of a core (in the given order) on
-// (size, loss) states: dominated states are dropped, states whose Lagrangian
-// bound exceeds UB are pruned, and with beam > 0 only the `beam` states of
-// best bound survive a layer (a heuristic pass).  Writes the option index of
-// every core class of the best final state (least loss, then least size,
-// then lexicographically smallest path).
+// (size, loss) states kept sorted by size.  A layer is the merge of the
+// previous layer shifted by each option's size (every shifted list is
+// already sorted), so it costs O(states x options); dominated states are
+// dropped during the merge, states whose Lagrangian bound exceeds UB are
+// pruned, and with beam > 0 only the `beam` states of best bound survive a
+// layer (a heuristic pass).  Writes the option index of every core class of
+// the best final state (least loss, then least size, then lexicographically
+// smallest path).
 int core_dp(const std::vector<std::vector<Opt>>& opts, double e_fixed, int64_t cap, double lambda,
             double UB, double tol, size_t beam, std::vector<int16_t>& pick) {
     const size_t n = opts.size();
     if (cap < 0) return MGS_EINFEASIBLE;
-    std::vector<double> mr(n + 1, 0.0);  // suffix sums of min(e + lambda s)
+    // per class: Lagrangian minimum m and the size of its (smallest) minimiser
+    std::vector<double> m(n, kInf);
+    std::vector<int64_t> sdef(n, 0);
+    for (size_t i = 0; i < n; ++i)
+        for (const Opt& x : opts[i]) {
+            const double v = x.e + lambda * (double)x.s;
+            if (v < m[i]) {
+                m[i] = v;
+                sdef[i] = x.s;
+            }
+        }
+    std::vector<double> mr(n + 1, 0.0);  // suffix sums of m
+    std::vector<int64_t> sr(n + 1, 0);   // suffix sums of sdef
     for (size_t i = n; i-- > 0;) {
-        double m = kInf;
-        for (const Opt& x : opts[i]) m = std::min(m, x.e + lambda * (double)x.s);
-        mr[i] = mr[i + 1] + m;
+        mr[i] = mr[i + 1] + m[i];
+        sr[i] = sr[i + 1] + sdef[i];
     }
+    Completion comp;
+    comp.build(opts, m, sdef, lambda);
     std::vector<std::vector<State>> layers;
     std::vector<State> cur{{0, 0.0, -1, -1}};
     std::vector<State> nxt;
+    std::vector<double> keys;
     size_t total_states = 1;
     for (size_t li = 0; li < n; ++li) {
-        nxt.clear();
-        for (int32_t si = 0; si < (int32_t)cur.size(); ++si) {
-            const State& st = cur[si];
-            for (const Opt& x : opts[li]) {
-                int64_t w = st.w + x.s;
-                if (w > cap) continue;
-                double z = st.z + x.e;
-                double lb = e_fixed + z + mr[li + 1] - lambda * (double)(cap - w);
-                if (lb > UB + tol) continue;
-                nxt.push_back({w, z, si, (int16_t)x.j});
-            }
-        }
-        layers.push_back(cur);
-        std::sort(nxt.begin(), nxt.end(), [](const State& a, const State& b) {
+        const std::vector<Opt>& o = opts[li];
+        const int nopt_l = (int)o.size();
+        const double rest = e_fixed + mr[li + 1];
+        comp.restrict_after((int64_t)li);
+        // bound of a state after this layer: Lagrangian part + completion LP
+        auto bound = [&](int64_t w, double z) {
+            return rest + z - lambda * (double)(cap - w) + comp.h(cap - w - sr[li + 1]);
+        };
+        // k-way merge of cur + o[j] by (size, loss); heap of the list heads
+        std::vector<int32_t> head(nopt_l, 0);
+        auto state_at = [&](int j, int32_t i) {
+            return State{cur[i].w + o[j].s, cur[i].z + o[j].e, i, (int16_t)o[j].j};
+        };
+        auto less = [&](const State& a, const State& b) {
             if (a.w != b.w) return a.w < b.w;
             return a.z < b.z;
-        });
-        cur.clear();
-        for (size_t i = 0; i < nxt.size(); ++i) {
-            const State& st = nxt[i];
-            if (!cur.empty()) {
-                State& last = cur.back();
-                if (st.z > last.z) continue;
-                if (st.z == last.z) {
+        };
+        // advance a head past states that overflow the capacity or the bound
+        auto valid = [&](int j, int32_t i) {
+            const State st = state_at(j, i);
+            if (st.w > cap) return 0;  // the list is sorted by size: stop this list
+            if (bound(st.w, st.z) > UB + tol) return 1;  // skip
+            return 2;
+        };
+        auto settle = [&](int j) {
+            while (head[j] < (int32_t)cur.size()) {
+                int v = valid(j, head[j]);
+                if (v == 0) {
+                    head[j] = (int32_t)cur.size();
+                    break;
+                }
+                if (v == 2) break;
+                ++head[j];
+            }
+        };
+        for (int j = 0; j < nopt_l; ++j) settle(j);
+        layers.push_back(cur);
+        nxt.clear();
+        for (;;) {
+            int bj = -1;
+            State best{};
+            for (int j = 0; j < nopt_l; ++j) {
+                if (head[j] >= (int32_t)cur.size()) continue;
+                State st = state_at(j, head[j]);
+                if (bj < 0 || less(st, best)) {
+                    best = st;
+                    bj = j;
+                }
+            }
+            if (bj < 0) break;
+            ++head[bj];
+            settle(bj);
+            if (!nxt.empty()) {
+                State& last = nxt.back();
+                if (best.z > last.z) continue;
+                if (best.z == last.z) {
                     // same loss with more size is dominated; same (size, loss) keeps
                     // the lexicographically smaller path: parents first, then option
-                    if (st.w == last.w) {
-                        bool less = st.prev == last.prev
-                                        ? st.opt < last.opt
-                                        : path_less(layers, layers.size() - 1, st.prev, last.prev);
-                        if (less) last = st;
+                    if (best.w == last.w) {
+                        bool lt = best.prev == last.prev
+                                      ? best.opt < last.opt
+                                      : path_less(layers, layers.size() - 1, best.prev, last.prev);
+                        if (lt) last = best;
                     }
                     continue;
                 }
+                if (best.w == last.w) {  // same size, strictly less loss: replace
+                    last = best;
+                    continue;
+                }
             }
-            cur.push_back(st);
+            nxt.push_back(best);
         }
-        if (beam && cur.size() > beam) {
-            std::nth_element(cur.begin(), cur.begin() + beam, cur.end(), [&](const State& a, const State& b) {
-                return a.z + lambda * (double)a.w < b.z + lambda * (double)b.w;
-            });
-            cur.resize(beam);
+        if (beam && nxt.size() > beam) {
+            // keep the `beam` states of least bound, in size order
+            keys.resize(nxt.size());
+            for (size_t i = 0; i < nxt.size(); ++i) keys[i] = bound(nxt[i].w, nxt[i].z);
+            std::vector<double> sel(keys);
+            std::nth_element(sel.begin(), sel.begin() + (beam - 1), sel.end());
+            const double cut = sel[beam - 1];
+            size_t w = 0;
+            for (size_t i = 0; i < nxt.size() && w < beam; ++i)
+                if (keys[i] <= cut) nxt[w++] = nxt[i];
+            nxt.resize(w);
         }
+        cur.swap(nxt);
         total_states += cur.size();
         if (total_states > kStateCap) return MGS_ELIMIT;
         if (cur.empty()) return MGS_EINFEASIBLE;
@@ -153,10 +315,30 @@ int core_dp(const std::vector<std::vector<Opt>>& opts, double e_fixed, int64_t c
     return MGS_OK;
 }
 
-int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_t budget,
-          uint8_t* choice, double* obj, int64_t* used) {
+// One multiple-choice knapsack instance: prepare() runs the LP relaxation
+// (and returns early when the unconstrained optimum fits), exact() the DP.
+struct Mckp {
+    const double* err;
+    const int64_t* size;
+    int64_t ncls;
+    int nopt;
+    int64_t budget;
+    std::vector<std::vector<Opt>> cls;
+    std::vector<int> inc_pos, lagbest;
+    std::vector<double> mlam, rcmin;
+    std::vector<int64_t> order;
+    double lambda = 0.0, LB0 = 0.0, UB = 0.0, tol = 0.0;
+    bool trivial = false;  // the unconstrained optimum fits the budget
+
+    Mckp(const double* e, const int64_t* s, int64_t n, int o, int64_t b)
+        : err(e), size(s), ncls(n), nopt(o), budget(b) {}
+
+    // Lower bound on the optimum (the optimum itself when trivial).
+    double lower_bound() const { return LB0; }
+
+    int prepare() {
     // ---- 1. per-class options without dominated ones, sorted by size
-    std::vector<std::vector<Opt>> cls(ncls);
+    cls.assign(ncls, {});
     int64_t min_total = 0;
     for (int64_t c = 0; c < ncls; ++c) {
         std::vector<Opt> o;
@@ -179,13 +361,10 @@ int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_
         int64_t tot = 0;
         for (auto& k : cls) tot += k.back().s;
         if (tot <= budget) {
+            trivial = true;
             double o = 0;
-            for (int64_t c = 0; c < ncls; ++c) {
-                choice[c] = (uint8_t)cls[c].back().j;
-                o += cls[c].back().e;
-            }
-            *obj = o;
-            *used = tot;
+            for (int64_t c = 0; c < ncls; ++c) o += cls[c].back().e;
+            LB0 = UB = o;
             return MGS_OK;
         }
     }
@@ -221,7 +400,7 @@ int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_
     std::stable_sort(incs.begin(), incs.end(), [](const Inc& a, const Inc& b) { return a.eff > b.eff; });
     std::vector<int> pos(ncls, 0);  // current option position per class
     int64_t cap = budget - min_total;
-    double lambda = 0.0;
+    lambda = 0.0;
     bool split = false;
     for (const Inc& in : incs) {
         if (pos[in.c] != in.from) continue;  // (cannot happen for a convex hull)
@@ -237,7 +416,7 @@ int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_
     }
     if (!split) lambda = 0.0;
     // incumbent: greedy solution improved by single-class moves
-    std::vector<int> inc_pos = pos;
+    inc_pos = pos;
     {
         bool improved = true;
         int rounds = 0;
@@ -263,13 +442,13 @@ int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_
             }
         }
     }
-    double UB = 0.0;
+    UB = 0.0;
     for (int64_t c = 0; c < ncls; ++c) UB += cls[c][inc_pos[c]].e;
 
     // ---- 3. Lagrangian bound, reduced costs, Lagrangian-best option per class
-    std::vector<double> mlam(ncls);
-    std::vector<int> lagbest(ncls, 0);
-    double LB0 = -lambda * (double)budget;
+    mlam.assign(ncls, 0.0);
+    lagbest.assign(ncls, 0);
+    LB0 = -lambda * (double)budget;
     double scale = std::fabs(UB);
     for (int64_t c = 0; c < ncls; ++c) {
         double m = kInf;
@@ -284,23 +463,44 @@ int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_
         LB0 += m;
         scale = std::max(scale, std::fabs(m));
     }
-    const double tol = 1e-9 * (scale + std::fabs(LB0) + std::fabs(lambda * (double)budget)) + 1e-300;
+    tol = 1e-9 * (scale + std::fabs(LB0) + std::fabs(lambda * (double)budget)) + 1e-300;
     // smallest reduced cost of any other option of the class
-    std::vector<double> rcmin(ncls, kInf);
+    rcmin.assign(ncls, kInf);
     for (int64_t c = 0; c < ncls; ++c)
         for (int i = 0; i < (int)cls[c].size(); ++i)
             if (i != lagbest[c])
                 rcmin[c] = std::min(rcmin[c], cls[c][i].e + lambda * (double)cls[c][i].s - mlam[c]);
-    std::vector<int64_t> order(ncls);
+    order.resize(ncls);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int64_t a, int64_t b) { return rcmin[a] < rcmin[b]; });
+    return MGS_OK;
+    }
 
+    int exact(uint8_t* choice, double* obj, int64_t* used) {
+        if (trivial) {
+            for (int64_t c = 0; c < ncls; ++c) choice[c] = (uint8_t)cls[c].back().j;
+        } else {
+            int rc = expand(choice);
+            if (rc) return rc;
+        }
+        double o = 0.0;
+        int64_t u = 0;
+        for (int64_t c = 0; c < ncls; ++c) {
+            o += err[c * nopt + choice[c]];
+            u += size[c * nopt + choice[c]];
+        }
+        *obj = o;
+        *used = u;
+        return MGS_OK;
+    }
+
+    int expand(uint8_t* choice) {
     // ---- 4. expanding core: DP over the classes whose alternatives are
     // cheapest in reduced cost improves the incumbent, which shrinks the gap;
     // once every class that can still change (rcmin <= gap) fits in the core,
     // one exact DP over exactly those classes finishes.
-    size_t K = 32;
+    size_t K = 128;
     for (;;) {
         const double gap = UB - LB0 + tol;
         std::vector<int64_t> need;
@@ -343,15 +543,16 @@ int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_
         }
         K *= 4;
     }
-    double o = 0.0;
-    int64_t u = 0;
-    for (int64_t c = 0; c < ncls; ++c) {
-        o += err[c * nopt + choice[c]];
-        u += size[c * nopt + choice[c]];
-    }
-    *obj = o;
-    *used = u;
     return MGS_OK;
+    }
+};
+
+int solve(const double* err, const int64_t* size, int64_t ncls, int nopt, int64_t budget,
+          uint8_t* choice, double* obj, int64_t* used) {
+    Mckp m(err, size, ncls, nopt, budget);
+    int rc = m.prepare();
+    if (rc) return rc;
+    return m.exact(choice, obj, used);
 }
 
 }  // namespace
@@ -386,8 +587,9 @@ extern "C" int mgs_size_table(const double* h_bits, const int64_t* h_n, int64_t 
 }
 
 extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const double* h_bits,
-                          int64_t budget_bits, int32_t size_mode, int32_t threads,
-                          int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used) {
+                          int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t flags,
+                          int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
+                          int32_t* h_status) {
     if (!d || !d->h_k || !d->h_bits || !h_err || !h_bits || !h_best_t || !h_best_bits || !h_obj ||
         !h_used)
         return MGS_EINVAL;
@@ -396,14 +598,22 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
         return MGS_EINVAL;
     const int C = d->C, T = d->T, G = d->G, nb = d->nb;
     int64_t kmax = 0;
-    for (int t = 0; t < T; ++t) kmax = std::max(kmax, d->h_k[t]);
+    for (int t = 0; t < T; ++t) {
+        if (d->h_k[t] < 0) return MGS_EINVAL;
+        kmax = std::max(kmax, d->h_k[t]);
+    }
     const int64_t gmaxn = (kmax + G - 1) / G;
     int b8 = -1;
     for (int i = 0; i < nb; ++i)
         if (d->h_bits[i] == 8) b8 = i;
-    std::vector<int> status(T, MGS_OK);
+    const int nthr = threads > 0 ? threads : omp_get_max_threads();
+    std::vector<int> st(T, MGS_OK), state(T, MGS_SEARCH_SOLVED);
+    std::vector<std::vector<double>> E(T);
+    std::vector<std::vector<int64_t>> S(T);
+    std::vector<std::unique_ptr<Mckp>> inst(T);
     std::vector<std::vector<uint8_t>> choice(T);
-#pragma omp parallel for schedule(dynamic, 1) num_threads(threads > 0 ? threads : omp_get_max_threads())
+    // ---- per ratio: tables, sizes, the doubled-8-bit test, LP bound
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
     for (int t = 0; t < T; ++t) {
         h_obj[t] = std::numeric_limits<double>::quiet_NaN();
         h_used[t] = 0;
@@ -411,49 +621,89 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
         const int64_t ng = (k + G - 1) / G;
         const int64_t ncls = (int64_t)C * ng;
         if (ncls == 0) {
-            status[t] = MGS_EINFEASIBLE;
+            state[t] = MGS_SEARCH_SKIPPED;
             continue;
         }
-        std::vector<double> e(ncls * nb), bt(ncls * nb);
-        std::vector<int64_t> n(ncls), sz(ncls * nb);
+        std::vector<double> bt(ncls * nb);
+        std::vector<int64_t> n(ncls);
+        E[t].resize(ncls * nb);
+        S[t].resize(ncls * nb);
         for (int c = 0; c < C; ++c)
             for (int64_t g = 0; g < ng; ++g) {
                 int64_t cls = (int64_t)c * ng + g;
                 int64_t slot = ((int64_t)t * C + c) * gmaxn + g;
                 n[cls] = std::min<int64_t>(G, k - g * G);
                 for (int i = 0; i < nb; ++i) {
-                    e[cls * nb + i] = h_err[slot * nb + i];
+                    E[t][cls * nb + i] = h_err[slot * nb + i];
                     bt[cls * nb + i] = h_bits[slot * nb + i];
                 }
             }
-        int rc = mgs_size_table(bt.data(), n.data(), ncls, nb, d->h_bits, size_mode, sz.data());
+        for (double v : E[t])
+            if (!std::isfinite(v)) st[t] = MGS_EINVAL;
+        if (st[t]) continue;
+        int rc = mgs_size_table(bt.data(), n.data(), ncls, nb, d->h_bits, size_mode, S[t].data());
         if (rc) {
-            status[t] = rc;
+            st[t] = rc;
             continue;
         }
-        // size of the all-8-bit configuration
-        int64_t s8 = 0;
+        int64_t s8 = 0;  // the all-8-bit configuration
         for (int64_t cls = 0; cls < ncls; ++cls)
-            s8 += (b8 >= 0) ? sz[cls * nb + b8] : n[cls] * 8 + kMetaBits;
+            s8 += (b8 >= 0) ? S[t][cls * nb + b8] : n[cls] * 8 + kMetaBits;
         if (2 * s8 < budget_bits) {
-            status[t] = MGS_EINFEASIBLE;
+            state[t] = MGS_SEARCH_SKIPPED;
             continue;
         }
-        choice[t].resize(ncls);
+        inst[t].reset(new Mckp(E[t].data(), S[t].data(), ncls, nb, budget_bits));
+        rc = inst[t]->prepare();
+        if (rc == MGS_EINFEASIBLE) state[t] = MGS_SEARCH_INFEASIBLE;
+        else st[t] = rc;
+    }
+    for (int t = 0; t < T; ++t)
+        if (st[t] != MGS_OK) return st[t];
+    // ---- exact solves: the ratio of least lower bound first, then (in
+    // parallel) every ratio whose bound does not exceed that optimum -- the
+    // others cannot win (or tie) -- unless every ratio is asked for.
+    std::vector<int> cand;
+    for (int t = 0; t < T; ++t)
+        if (state[t] == MGS_SEARCH_SOLVED) cand.push_back(t);
+    std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+        return inst[a]->lower_bound() < inst[b]->lower_bound();
+    });
+    auto solve_one = [&](int t) {
+        choice[t].resize(inst[t]->ncls);
         double o = 0;
         int64_t u = 0;
-        rc = mgs_ilp_solve(e.data(), sz.data(), ncls, nb, budget_bits, choice[t].data(), &o, &u);
-        status[t] = rc;
+        int rc = inst[t]->exact(choice[t].data(), &o, &u);
+        st[t] = rc;
         if (rc == MGS_OK) {
             h_obj[t] = o;
             h_used[t] = u;
         }
+    };
+    std::vector<int> todo;
+    if (flags & MGS_SEARCH_ALL) {
+        todo = cand;
+    } else if (!cand.empty()) {
+        solve_one(cand[0]);
+        if (st[cand[0]] != MGS_OK) return st[cand[0]];
+        const double best0 = h_obj[cand[0]];
+        for (size_t i = 1; i < cand.size(); ++i) {
+            const int t = cand[i];
+            if (inst[t]->lower_bound() <= best0 + inst[t]->tol + 1e-12 * std::fabs(best0))
+                todo.push_back(t);
+            else
+                state[t] = MGS_SEARCH_PRUNED;
+        }
     }
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+    for (int i = 0; i < (int)todo.size(); ++i) solve_one(todo[i]);
     for (int t = 0; t < T; ++t)
-        if (status[t] != MGS_OK && status[t] != MGS_EINFEASIBLE) return status[t];
+        if (st[t] != MGS_OK) return st[t];
+    if (h_status)
+        for (int t = 0; t < T; ++t) h_status[t] = state[t];
     int best = -1;
     for (int t = 0; t < T; ++t) {
-        if (status[t] != MGS_OK) continue;
+        if (state[t] != MGS_SEARCH_SOLVED) continue;
         if (best < 0 || h_obj[t] < h_obj[best] ||
             (h_obj[t] == h_obj[best] &&
              (d->h_k[t] > d->h_k[best] || (d->h_k[t] == d->h_k[best] && t > best))))

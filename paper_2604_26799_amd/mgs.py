@@ -49,7 +49,7 @@ SIGNATURES = {
     "mgs_vq_assign": (ct.c_int, [P, I64, I32, P, I32, P, P, P, P, SZ, P]),
     "mgs_ilp_solve": (ct.c_int, [P, P, I64, I32, I64, P, P, P]),
     "mgs_size_table": (ct.c_int, [P, P, I64, I32, P, I32, P]),
-    "mgs_search": (ct.c_int, [P, P, P, I64, I32, I32, P, P, P, P]),
+    "mgs_search": (ct.c_int, [P, P, P, I64, I32, I32, I32, P, P, P, P, P]),
 }
 
 
@@ -249,12 +249,17 @@ def size_table(bits_table: np.ndarray, n_per_group=None, bit_list=None, mode: in
     return out
 
 
+SEARCH_ALL = 1
+SEARCH_SOLVED, SEARCH_SKIPPED, SEARCH_INFEASIBLE, SEARCH_PRUNED = 0, 1, 2, 3
+
+
 def search(N: int, C: int, k, G: int, bits, err: np.ndarray, bits_table: np.ndarray, budget_bits: int,
-           size_mode: int = 0, threads: int = 0):
+           size_mode: int = 0, threads: int = 0, solve_all: bool = False):
     """Reserve-ratio loop + exact ILP over host copies of a sweep's tables.
 
-    Returns dict(best_t, best_bits u8[C][ng], obj f64[T], used i64[T]); best_t is -1
-    when no ratio is admissible.
+    Returns dict(best_t, best_bits u8[C][ng], obj f64[T], used i64[T], status i32[T]);
+    best_t is -1 when no ratio is admissible.  Without ``solve_all`` ratios whose LP
+    bound exceeds the best optimum are not solved (status SEARCH_PRUNED).
     """
     d = sweep_desc(N, C, k, G, bits)
     err = np.ascontiguousarray(err, dtype=np.float64)
@@ -266,11 +271,13 @@ def search(N: int, C: int, k, G: int, bits, err: np.ndarray, bits_table: np.ndar
     best_bits = np.zeros(C * max(ngmax, 1), dtype=np.uint8)
     obj = np.empty(T, dtype=np.float64)
     used = np.empty(T, dtype=np.int64)
+    status = np.empty(T, dtype=np.int32)
     code = lib().mgs_search(ct.byref(d), _np_ptr(err), _np_ptr(bt), int(budget_bits), size_mode, threads,
-                            ct.byref(best_t), _np_ptr(best_bits), _np_ptr(obj), _np_ptr(used))
+                            SEARCH_ALL if solve_all else 0, ct.byref(best_t), _np_ptr(best_bits),
+                            _np_ptr(obj), _np_ptr(used), _np_ptr(status))
     if code not in (OK, EINFEASIBLE):
         _check(code, "mgs_search")
     t = best_t.value
     ng = (int(kk[t]) + G - 1) // G if t >= 0 else 0
     return {"best_t": t, "best_bits": best_bits[:C * ng].reshape(C, ng) if t >= 0 else None,
-            "obj": obj, "used": used}
+            "obj": obj, "used": used, "status": status}

@@ -114,7 +114,14 @@ def test_search_vs_oracle(orc):
     raw_bits = w.n * w.channels * 32
     for ratio in (8, 12, 20, 40):
         budget = raw_bits // ratio
-        res = mgs.search(w.n, w.channels, k, w.group, w.bits, tab["err"], tab["bits"], budget)
+        res = mgs.search(w.n, w.channels, k, w.group, w.bits, tab["err"], tab["bits"], budget, solve_all=True)
+        fast = mgs.search(w.n, w.channels, k, w.group, w.bits, tab["err"], tab["bits"], budget)
+        assert fast["best_t"] == res["best_t"]
+        if res["best_t"] >= 0:
+            assert np.array_equal(fast["best_bits"], res["best_bits"])
+            # ratios left unsolved had a lower bound above the chosen optimum
+            for t in np.where(fast["status"] == mgs.SEARCH_PRUNED)[0]:
+                assert res["obj"][t] > res["obj"][res["best_t"]]
         rows = []
         for t in range(len(k)):
             ng = (int(k[t]) + w.group - 1) // w.group
