@@ -114,6 +114,28 @@ int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float
                     const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
                     float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes, void* stream);
 
+/*
+ * Launch shape of the sweep kernel (threads per workgroup, elements per
+ * thread, LDS bytes the histogram plan may use (0 = the device maximum),
+ * channels per workgroup tile (0 = all channels)).
+ * mgs_sweep_autotune times every candidate shape on the given inputs (each
+ * `reps` times, HIP events on `stream`, minimum kept), registers the fastest
+ * for (G, nb, max bit-width) in a process-wide table used by later sweeps,
+ * and leaves the tables computed with it.  It synchronises the stream, so it
+ * must not be called during graph capture.  h_ms[i] / h_shapes[i][4]
+ * (optional, mgs_sweep_shape_count() entries) receive each candidate's time
+ * (-1 when it does not apply) and shape; h_best[4] (optional) the chosen one.
+ * mgs_sweep_set_shape registers a shape by hand (nt == 0 clears the entry).
+ * Results are identical for every shape.
+ */
+int mgs_sweep_shape_count(void);
+int mgs_sweep_autotune(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                       const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                       float* d_gmax, void* d_ws, size_t ws_bytes, void* stream, int32_t reps,
+                       float* h_ms, int32_t* h_shapes, int32_t* h_best);
+int mgs_sweep_set_shape(int32_t G, int32_t nb, int32_t bmax, int32_t nt, int32_t ept,
+                        int32_t lds_cap, int32_t cpb);
+
 /* ======================================================================
  * Final quantization at a chosen bit allocation, and its inverse (paper:
  * section "Group-wise Attribute Quantization"; the stored metadata are the

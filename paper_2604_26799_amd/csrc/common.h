@@ -42,6 +42,26 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     for (int o = 32; o >= 1; o >>= 1) v = v + __shfl_xor(v, o, MGS_WAVE);
     return v;
 }
+// FP64 sum over the wavefront with DPP row shifts and row broadcasts (no LDS
+// traffic); the fixed pattern makes the result deterministic.  Returns the
+// total in every lane (read from lane 63).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_total_f64(double v) {
+    v += dpp_f64<0x111, 0xF>(v);  // row_shr:1   (inclusive prefix within rows of 16)
+    v += dpp_f64<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_f64<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_f64<0x118, 0xF>(v);  // row_shr:8   -> lane 15 of each row: row sum
+    v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3 -> lane 63: total
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, MGS_WAVE);

@@ -7,6 +7,8 @@ namespace mgs {
 
 constexpr int LGTAB = 256;            // h * log2(h) table entries kept in LDS
 constexpr int MGS_MAX_ENTRIES = 40;   // histogram windows per plan
+constexpr int REPL_WORDS = 1024;      // words a replicated low-b histogram may take
+constexpr int REPL_MAX_LOG = 5;       // at most 32 copies per bin
 
 // One histogram window of one bit-width inside a batch of LDS words.
 struct HistEntry {
@@ -14,7 +16,9 @@ struct HistEntry {
     uint8_t packed;   // two 16-bit bins per 32-bit word
     uint8_t first;    // first window of this b: it also accumulates the loss
     uint8_t split;    // the b's bins span more than one window
-    uint8_t pad[3];
+    uint8_t rtn;      // entropy from the atomics' old counts (no scan of the bins)
+    uint8_t rlog;     // log2 of the copies per bin (lane-interleaved replicas)
+    uint8_t pad;
     int32_t lo;       // first word of the window within the b's words
     int32_t nwords;   // words in the window
     int32_t lds_off;  // word offset of the window inside the batch
@@ -45,7 +49,8 @@ struct SceneDesc {
     uint8_t bl[MGS_MAX_BITS];
 };
 
-// A tile of a multi-scene work list.
+// A tile of a multi-scene work list: ratio t, group g, channels
+// [c, min(C, c + cpb)).
 struct TileRef {
     int32_t scene;
     int32_t t;
@@ -57,10 +62,13 @@ struct TileRef {
 struct SweepParams {
     mgs_status_block* status;
     const SceneDesc* scenes;  // device array (workspace)
-    const double* lgtab;      // h * log2(h) for h in [0, lgtab_max] (workspace)
+    const double* lgtab;      // T(h) = h log2 h for h in [0, lgtab_max], then the increments
+                              // F[c] = R(T(c+1)) - R(T(c)), R: rounding to the grid 2^-K
     int64_t ntiles;
-    int32_t lgtab_max, pad0;
-    int32_t nbatches, nentries, max_batch_words, pad;
+    int32_t lgtab_max;
+    int32_t cpb;              // channels per tile
+    int32_t nbatches, nentries, max_batch_words;
+    int32_t kgrid;            // K of the increment grid
     int32_t batch_begin[MGS_MAX_ENTRIES + 1];
     int32_t batch_words[MGS_MAX_ENTRIES];
     HistEntry entries[MGS_MAX_ENTRIES];
@@ -69,13 +77,14 @@ struct SweepParams {
 // Launch shape and LDS capacity of the sweep kernel.
 struct Shape {
     int nt;        // threads per workgroup
-    int ept;       // elements per thread (nt * ept >= G)
+    int ept;       // elements per thread (nt * ept >= G, else the chunked kernel)
     int lds_cap;   // LDS bytes the histogram plan may use (0 = device maximum)
+    int cpb = 0;   // channels per tile (0 = all channels)
 };
 
 int fill_scene(const mgs_sweep_desc* d, const float* attr, const float* imp, const int32_t* kept,
                double* err, double* bits, float* gmin, float* gmax, uint32_t* hist, SceneDesc* sc);
-bool build_plan(const uint8_t* bl, int nb, int cap_words, SweepParams* p);
+bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p);
 int plan_for(const SceneDesc& sc, const Shape& sh, SweepParams* p, size_t* lds_bytes);
 Shape default_shape(int G, int nb, int bmax);
 bool shape_valid(const Shape& sh, int G);
@@ -83,6 +92,9 @@ bool shape_valid(const Shape& sh, int G);
 // tables (NaN padding, status reset, debug histogram clearing).
 int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
                 mgs_status_block* status, double* lgtab, int lgtab_max, hipStream_t s);
+// Grid exponent K of the entropy increments: every partial sum of up to G
+// increments stays an exact FP64 multiple of 2^-K.
+int increment_grid_bits(int G);
 // G: the largest group size of the launch (selects the chunked kernel when
 // it exceeds the shape's nt * ept).
 int launch_sweep(const SweepParams& p, const TileRef* tiles, const Shape& sh, size_t lds,

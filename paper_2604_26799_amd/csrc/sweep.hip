@@ -8,14 +8,17 @@
 // errors per group and b.  Size table (section "Size Estimator"): Shannon
 // bound n * H of the group's codes, in bits.
 //
-// One workgroup owns one tile (ratio t, channel c, group g).  It gathers the
-// group's values and weights into registers once, reduces min / max, and
-// then evaluates every candidate b from those registers: quantize,
-// dequantize, error, and an LDS histogram of the codes.  Histograms are
-// laid out in LDS per "batch" of bit-widths that fit together; a b whose
-// 2^b bins exceed the LDS capacity is split into bin windows counted in
-// separate passes.  Bins are 32-bit counters, or two 16-bit counters per
-// word where that is needed to fit (counts never exceed G <= 65535).
+// One workgroup owns one tile (ratio t, group g, a run of channels).  Per
+// channel it gathers the group's values and weights into registers, reduces
+// min / max, and then evaluates every candidate b from those registers:
+// quantize, dequantize, error, and an LDS histogram of the codes.
+// Histograms are laid out in LDS per "batch" of bit-widths that fit
+// together; a b whose 2^b bins exceed the LDS capacity is split into bin
+// windows counted in separate passes.  Bins are 32-bit counters, or two
+// 16-bit counters per word where that is needed to fit (counts never exceed
+// G <= 65535).  Histograms with few bins keep up to 32 lane-interleaved
+// copies of every bin, so that the many lanes of a wavefront that land in
+// one bin do not serialise on one LDS address; the scan adds the copies.
 //
 // Bit exactness of the codes.  The quantizer is evaluated with single FP32
 // operations, round-half-even, no contraction (built -ffp-contract=off) and
@@ -32,12 +35,21 @@
 //      half-even, the clamp bounds are integers and fl() is monotone.  With
 //      |Z| <= 2^23, fl(q - Z) is fl((t' ) - (2^23 + Z)) because both
 //      operands are exact.
-// The loss uses FP64 per term, d = (double)xhat - (double)x exactly, and
-// accumulates in a fixed order (lane, wave, then waves in index order), so
-// results are deterministic and within ~1e-13 of an in-order FP64 sum.
-// The size is n log2 n - sum_k h_k log2 h_k in FP64 (h log2 h from an LDS
-// table for h < 256), which equals sum_k h_k log2(n / h_k) to ~1e-12
-// relative.
+// Loss.  On those fast groups the values and steps are scaled by 2^-E with
+// 2^E <= R < 2^(E+1); both scalings are exact, so the FP32 dequantized value
+// is exactly xhat * 2^-E and every difference stays far from FP32 overflow
+// and underflow.  Each thread forms d = fl(xhat' - x'), and sums w * d^2
+// over its <= EPT elements in FP32 (relative error <= (EPT + 3) * 2^-24);
+// the partials are rescaled by 2^(2E) and reduced in FP64 in a fixed order,
+// so results are deterministic.  Literal-division groups and underflowed
+// steps keep exact FP64 terms.
+// Size.  n log2 n - sum_k h_k log2 h_k in FP64.  Scanned histograms take
+// h log2 h per bin (LDS table for h < 256).  Histograms with more bins than
+// half the group instead add, per element, the increment of its bin's old
+// count c (returned by the atomic): F[c] = R(T(c+1)) - R(T(c)) with
+// T(h) = h log2 h and R the rounding to a 2^-K grid, so a bin's increments
+// telescope to R(T(h)) exactly and in any order.  The LDS copy of F covers
+// c < 255; rarer larger counts are settled by a correction scan.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -50,69 +62,102 @@
 
 namespace mgs {
 
-// h * log2(h): small h from the LDS copy, larger h from the workspace table
-// (both written from the same FP64 evaluation by the init kernel).
+// h * log2(h) of a bin count (scanned histograms): small counts from the
+// LDS copy, larger ones from the workspace table.
 __device__ __forceinline__ double hlog2h(uint32_t h, const double* lg, const double* lgt) {
-    if (h < 2u) return 0.0;
-    if (h < (uint32_t)LGTAB) return lg[h];
-    return lgt[h];
+    double v = lg[h < (uint32_t)LGTAB ? h : 0u];
+    if (h >= (uint32_t)LGTAB) v = lgt[h];
+    return v;
 }
 
-// FP64 value of a per-element copy.  For FP32 copies an empty asm with a
-// register constraint keeps the compiler from hoisting the conversion out of
-// the bit-width loop (which would double the registers the copy takes).
-template <typename XT>
-__device__ __forceinline__ double as_f64(XT v) {
-    if constexpr (sizeof(XT) == 4) asm volatile("" : "+v"(v));
+// FP64 value of a per-element FP32 copy.  The empty asm keeps the compiler
+// from hoisting the conversion out of the bit-width loop, which would hold a
+// second, FP64 copy of every element in registers.
+__device__ __forceinline__ double as_f64(float v) {
+    asm volatile("" : "+v"(v));
     return (double)v;
 }
 
-// One histogram-window pass over the tile's elements for one bit-width on
-// the fast path (x / S_b from x / R, 2^23 rounding trick), specialised on
-// packed bins, ragged group and whether the loss is accumulated here.
-template <int NT, int EPT, typename XT, bool PACKED, bool CHECK, bool ERR>
-__device__ __forceinline__ double eval_fast(const float (&u)[EPT], const XT (&xd)[EPT],
-                                            const XT (&wd)[EPT], int n, int tid, float P,
-                                            float S, float Z, uint32_t* hist, int base) {
+// Rounds to the grid 2^-K on which the entropy increments live.
+__device__ __forceinline__ double grid_round(double v, int K) {
+    return ldexp(rint(ldexp(v, K)), -K);
+}
+
+// Partial sums of one evaluation pass in one thread: the loss in FP32 (fast
+// paths, values scaled by 2^-E, so the terms stay far from FP32 overflow and
+// underflow) or in FP64 (literal-division and underflowed-step paths), and
+// the entropy increments (FP64, exact grid sum).
+struct Part {
+    float err;
+    double err64;
+    double ent;
+};
+
+// Entropy increment of one more element in a bin that held c before: the
+// LDS table covers c < LGTAB - 1; its last entry is 0 and flags the rare
+// bins that grow past it, which the correction scan settles afterwards.
+__device__ __forceinline__ void add_increment(uint32_t c, const double* lf, Part& acc,
+                                              uint32_t& ovf) {
+    acc.ent += lf[c < (uint32_t)(LGTAB - 1) ? c : (uint32_t)(LGTAB - 1)];
+    ovf |= (uint32_t)(c >= (uint32_t)(LGTAB - 1));
+}
+
+// One histogram pass over the tile's elements for one bit-width on the fast
+// path (x / S_b from x / R, 2^23 rounding trick), specialised on packed bins,
+// ragged group and incremental entropy (RTN: the atomic's old count c gives
+// the entropy increment F[c]; no scan of the bins afterwards).
+// xv holds x * 2^-E and Ss = S * 2^-E: both scalings are exact, so the
+// dequantized value (q - Z) * Ss is exactly xhat * 2^-E.
+// REPL: 2^rl copies of every bin, bin q of lane l in word (q << rl) | cpy with
+// cpy = l mod 2^rl, so lanes that share a bin hit different LDS banks.
+template <int NT, int EPT, bool PACKED, bool CHECK, bool RTN, bool REPL>
+__device__ __forceinline__ Part eval_fast(const float (&u)[EPT], const float (&xv)[EPT],
+                                          const float (&wv)[EPT], int n, int tid, float P, float Ss,
+                                          float Z, uint32_t* hist, int base, int rl, int cpy,
+                                          const double* lf, uint32_t& ovf) {
     const float M = 8388608.0f;  // 2^23
     const float MZ = M + Z;
     const float hi = M + (P - 1.0f);
-    double acc = 0.0;
+    Part acc{0.0f, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
         if (CHECK && i * NT + tid >= n) continue;
         float t = __builtin_fmaf(u[i], P, Z);
         float tm = __builtin_amdgcn_fmed3f(t + M, M, hi);
         uint32_t qi = __float_as_uint(tm) - 0x4B000000u;
-        if (PACKED)
-            atomicAdd(&hist[base + (int)(qi >> 1)], 1u << ((qi & 1u) << 4));
-        else
-            atomicAdd(&hist[base + (int)qi], 1u);
-        if (ERR) {
-            float xh = (tm - MZ) * S;
-            double d = (double)xh - as_f64(xd[i]);
-            acc = __builtin_fma(as_f64(wd[i]), d * d, acc);
+        if (PACKED) {
+            const uint32_t sh = (qi & 1u) << 4;
+            const uint32_t old = atomicAdd(&hist[base + (int)(qi >> 1)], 1u << sh);
+            if (RTN) add_increment((old >> sh) & 0xFFFFu, lf, acc, ovf);
+        } else {
+            const int word = REPL ? (((int)qi << rl) | cpy) : (int)qi;
+            const uint32_t old = atomicAdd(&hist[base + word], 1u);
+            if (RTN) add_increment(old, lf, acc, ovf);
         }
+        float xh = (tm - MZ) * Ss;
+        float d = xh - xv[i];
+        acc.err = __builtin_fmaf(wv[i], d * d, acc.err);
     }
     return acc;
 }
 
 // The same pass for the rare cases, with runtime switches: bins split into
 // windows, |Z| > 2^23 (rint path) or the literal division per element.
-template <int NT, int EPT, typename XT>
-__device__ __forceinline__ double eval_generic(const float (&u)[EPT], const XT (&xd)[EPT],
-                                            const XT (&wd)[EPT], int n, int tid, float P,
-                                            float S, float Z, uint32_t* hist, int base, int lo,
-                                            int nwords, bool packed, bool literal, bool err) {
+// Literal tiles are never scaled (E = 0, Ss = S) and keep the loss in FP64.
+template <int NT, int EPT>
+__device__ __forceinline__ Part eval_generic(const float (&u)[EPT], const float (&xv)[EPT],
+                                             const float (&wv)[EPT], int n, int tid, float P, float S,
+                                             float Ss, float Z, uint32_t* hist, int base, int lo,
+                                             int nwords, bool packed, int rl, int cpy, bool literal,
+                                             bool err, bool rtn, const double* lf, uint32_t& ovf) {
     const float qmax = P - 1.0f;
-    double acc = 0.0;
+    Part acc{0.0f, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
         if (i * NT + tid >= n) continue;
         float t;
         if (literal) {
-            float x = (float)xd[i];
-            t = x / S;
+            t = xv[i] / S;
             t = t + Z;
         } else {
             t = __builtin_fmaf(u[i], P, Z);
@@ -120,39 +165,62 @@ __device__ __forceinline__ double eval_generic(const float (&u)[EPT], const XT (
         t = __builtin_amdgcn_fmed3f(t, 0.0f, qmax);
         float q = __builtin_rintf(t);
         uint32_t qi = (uint32_t)q;
-        int word = packed ? (int)(qi >> 1) : (int)qi;
-        uint32_t inc = packed ? (1u << ((qi & 1u) << 4)) : 1u;
-        if ((uint32_t)(word - lo) < (uint32_t)nwords) atomicAdd(&hist[base + word], inc);
+        int word = packed ? (int)(qi >> 1) : (((int)qi << rl) | cpy);
+        uint32_t sh = packed ? ((qi & 1u) << 4) : 0u;
+        if ((uint32_t)(word - lo) < (uint32_t)nwords) {
+            uint32_t old = atomicAdd(&hist[base + word], 1u << sh);
+            if (rtn) add_increment((old >> sh) & 0xFFFFu, lf, acc, ovf);
+        }
         if (err) {
-            float xh = (q - Z) * S;
-            double d = (double)xh - as_f64(xd[i]);
-            acc = __builtin_fma(as_f64(wd[i]), d * d, acc);
+            float xh = (q - Z) * Ss;
+            if (literal) {
+                double d = (double)xh - as_f64(xv[i]);
+                acc.err64 = __builtin_fma(as_f64(wv[i]), d * d, acc.err64);
+            } else {
+                float d = xh - xv[i];
+                acc.err = __builtin_fmaf(wv[i], d * d, acc.err);
+            }
         }
     }
     return acc;
 }
 
-template <int NT, int EPT, typename XT, bool PACKED>
-__device__ __forceinline__ double eval_fast_dispatch(bool check, bool err, const float (&u)[EPT],
-                                                     const XT (&xd)[EPT],
-                                                     const XT (&wd)[EPT], int n, int tid,
-                                                     float P, float S, float Z, uint32_t* hist,
-                                                     int base) {
-    if (check) {
-        if (err) return eval_fast<NT, EPT, XT, PACKED, true, true>(u, xd, wd, n, tid, P, S, Z, hist, base);
-        return eval_fast<NT, EPT, XT, PACKED, true, false>(u, xd, wd, n, tid, P, S, Z, hist, base);
+template <int NT, int EPT, bool PACKED>
+__device__ __forceinline__ Part eval_fast_dispatch(bool check, bool rtn, int rl, int cpy,
+                                                   const float (&u)[EPT], const float (&xv)[EPT],
+                                                   const float (&wv)[EPT], int n, int tid, float P,
+                                                   float S, float Z, uint32_t* hist, int base,
+                                                   const double* lf, uint32_t& ovf) {
+#define MGS_EVAL(CHK, RT, RP) \
+    eval_fast<NT, EPT, PACKED, CHK, RT, RP>(u, xv, wv, n, tid, P, S, Z, hist, base, rl, cpy, lf, ovf)
+    if constexpr (PACKED) {
+        if (check) return rtn ? MGS_EVAL(true, true, false) : MGS_EVAL(true, false, false);
+        return rtn ? MGS_EVAL(false, true, false) : MGS_EVAL(false, false, false);
+    } else {
+        // replicated bins only ever appear on scanned (non-incremental) entries
+        if (check) {
+            if (rtn) return MGS_EVAL(true, true, false);
+            return rl ? MGS_EVAL(true, false, true) : MGS_EVAL(true, false, false);
+        }
+        if (rtn) return MGS_EVAL(false, true, false);
+        return rl ? MGS_EVAL(false, false, true) : MGS_EVAL(false, false, false);
     }
-    if (err) return eval_fast<NT, EPT, XT, PACKED, false, true>(u, xd, wd, n, tid, P, S, Z, hist, base);
-    return eval_fast<NT, EPT, XT, PACKED, false, false>(u, xd, wd, n, tid, P, S, Z, hist, base);
+#undef MGS_EVAL
 }
 
+// Waves per SIMD the register budget must allow: <= 128 VGPRs for shapes
+// that hold 16 or fewer elements per thread, so that two 512-thread blocks
+// (or four of 256) share a CU when their histograms fit in LDS.
 template <int NT, int EPT, bool CHUNKED>
-__global__ __launch_bounds__(NT) void sweep_kernel(SweepParams p, const TileRef* __restrict__ tiles) {
+constexpr int sweep_min_waves() { return (EPT <= 16 && !CHUNKED) ? 4 : 1; }
+
+template <int NT, int EPT, bool CHUNKED>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<NT, EPT, CHUNKED>())))
+void sweep_kernel(SweepParams p, const TileRef* __restrict__ tiles) {
     constexpr int NW = NT / MGS_WAVE;
-    // per-element copies: FP64 when registers allow, else FP32 converted per use
-    using XT = typename std::conditional<(EPT <= 8), double, float>::type;
     extern __shared__ uint32_t hist[];
     __shared__ double lg[LGTAB];
+    __shared__ double lf[LGTAB];
     __shared__ double errpart[MGS_MAX_BITS][NW];
     __shared__ double bitpart[MGS_MAX_BITS][NW];
     __shared__ float red_mn[NW], red_mx[NW];
@@ -164,216 +232,286 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepParams p, const TileRef*
     const int wave = tid / MGS_WAVE;
 
     const double* __restrict__ lgt = p.lgtab;
-    for (int h = tid; h < LGTAB; h += NT) lg[h] = h <= p.lgtab_max ? lgt[h] : 0.0;
+    const double* __restrict__ lft = p.lgtab + (p.lgtab_max + 1);
+    for (int h = tid; h < LGTAB; h += NT) {
+        lg[h] = h <= p.lgtab_max ? lgt[h] : 0.0;
+        lf[h] = (h <= p.lgtab_max && h < LGTAB - 1) ? lft[h] : 0.0;
+    }
+    // grid value of T(LGTAB - 1), the start of every correction
+    const double rt_top = grid_round(lgt[min(LGTAB - 1, p.lgtab_max)], p.kgrid);
 
     for (int64_t it = blockIdx.x; it < p.ntiles; it += gridDim.x) {
-        // ---- locate the tile
-        int t, c, g;
+        // ---- locate the tile: (ratio t, group g) for channels [c0, c1)
+        int t, c0, g;
         const SceneDesc* sc;
         if (tiles) {
             TileRef tr = tiles[it];
             sc = &p.scenes[tr.scene];
             t = tr.t;
-            c = tr.c;
+            c0 = tr.c;
             g = tr.g;
         } else {
             sc = &p.scenes[0];
-            int64_t gpc = sc->gpc;
-            c = (int)(it / gpc);
-            int r = (int)(it - (int64_t)c * gpc);
+            const int64_t gpc = sc->gpc;
+            const int cc = (int)(it / gpc);
+            const int r = (int)(it - (int64_t)cc * gpc);
+            c0 = cc * p.cpb;
             t = 0;
             while (t + 1 < sc->T && sc->gcum[t + 1] <= r) ++t;
             g = r - sc->gcum[t];
         }
+        const int c1 = min(sc->C, c0 + p.cpb);
         const int64_t j0 = (int64_t)g * sc->G;
         const int64_t krem = sc->k[t] - j0;
         const int n = (int)(krem < sc->G ? krem : sc->G);
         const int32_t* J = sc->kept + sc->koff[t] + j0;
-        const float* row = sc->attr + (int64_t)c * sc->ld;
-        const int64_t slot = ((int64_t)t * sc->C + c) * sc->gmaxn + g;
         const int nb = sc->nb;
 
-        // ---- gather values and weights, min / max, finiteness.  A group
-        // larger than the block's register capacity (NT * EPT) is processed
-        // in chunks that are gathered again for every histogram batch.
+        // ---- per-element state, gathered per channel into registers (a
+        // group beyond NT * EPT elements -- the chunked kernel -- is gathered
+        // per chunk, again for every histogram batch).  The indices and weights
+        // of a tile's later channels come from L1/L2.
         constexpr int CAP = NT * EPT;
-        // (the non-chunked instantiation is only launched when G <= CAP)
         const int nchunk = CHUNKED ? (n + CAP - 1) / CAP : 1;
-        float u[EPT];
-        XT xd[EPT], wd[EPT];
-        float mn = INFINITY, mx = -INFINITY;
-        uint32_t bad = 0;
-        auto gather = [&](int ch) {
+        float u[EPT], xv[EPT], wv[EPT];
+
+        const float* imp = sc->imp;
+        for (int c = c0; c < c1; ++c) {
+            // Opaque copies of the index and weight pointers: otherwise their
+            // loads are hoisted out of the channel loop and held in registers
+            // across all channels, which halves the occupancy.
+            const int32_t* Jc = J;
+            const float* impc = imp;
+            asm volatile("" : "+v"(Jc), "+v"(impc));
+            const float* row = sc->attr + (int64_t)c * sc->ld;
+            const int64_t slot = ((int64_t)t * sc->C + c) * sc->gmaxn + g;
+            float mn = INFINITY, mx = -INFINITY;
+            uint32_t bad = 0;
+            auto gather = [&](int ch) {
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                int j = ch * CAP + i * NT + tid;
-                float x = 0.0f, w = 0.0f;
-                if (j < n) {
-                    int32_t idx = J[j];
-                    x = row[idx];
-                    w = sc->imp[idx];
-                    bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
-                    mn = fminf(mn, x);
-                    mx = fmaxf(mx, x);
+                for (int i = 0; i < EPT; ++i) {
+                    int j = ch * CAP + i * NT + tid;
+                    float x = 0.0f, w = 0.0f;
+                    if (j < n) {
+                        int32_t id = Jc[j];
+                        x = row[id];
+                        w = impc[id];
+                        bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
+                        mn = fminf(mn, x);
+                        mx = fmaxf(mx, x);
+                    }
+                    xv[i] = x;
+                    wv[i] = w;
                 }
-                xd[i] = (XT)x;
-                wd[i] = (XT)w;
+            };
+            if constexpr (CHUNKED) {
+                for (int ch = nchunk - 1; ch >= 0; --ch) gather(ch);  // ends holding chunk 0
+            } else {
+                gather(0);
             }
-        };
-        if constexpr (CHUNKED) {
-            for (int ch = nchunk - 1; ch >= 0; --ch) gather(ch);  // ends holding chunk 0
-        } else {
-            gather(0);
-        }
-        mn = wave_min_f32(mn);
-        mx = wave_max_f32(mx);
-        bad = wave_or_u32(bad);
-        if (lane == 0) {
-            red_mn[wave] = mn;
-            red_mx[wave] = mx;
-            red_bad[wave] = bad;
-        }
-        __syncthreads();
-        mn = red_mn[0];
-        mx = red_mx[0];
-        bad = red_bad[0];
+            mn = wave_min_f32(mn);
+            mx = wave_max_f32(mx);
+            bad = wave_or_u32(bad);
+            if (lane == 0) {
+                red_mn[wave] = mn;
+                red_mx[wave] = mx;
+                red_bad[wave] = bad;
+            }
+            __syncthreads();
+            mn = red_mn[0];
+            mx = red_mx[0];
+            bad = red_bad[0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            mn = fminf(mn, red_mn[w]);
-            mx = fmaxf(mx, red_mx[w]);
-            bad |= red_bad[w];
-        }
-        const float R = mx - mn;
-        if (!finite_f32(R)) bad = 1;
-        if (tid == 0) {
-            sc->gmin[slot] = mn;
-            sc->gmax[slot] = mx;
-        }
-        if (bad || R == 0.0f) {
-            // non-finite group: NaN tables and the status flag; constant
-            // group: every code 0, zero loss and zero size.
+            for (int w = 1; w < NW; ++w) {
+                mn = fminf(mn, red_mn[w]);
+                mx = fmaxf(mx, red_mx[w]);
+                bad |= red_bad[w];
+            }
+            const float R = mx - mn;
+            if (!finite_f32(R)) bad = 1;
+            if (tid == 0) {
+                sc->gmin[slot] = mn;
+                sc->gmax[slot] = mx;
+            }
+            if (bad || R == 0.0f) {
+                // non-finite group: NaN tables and the status flag; constant
+                // group: every code 0, zero loss and zero size.
+                if (tid < nb) {
+                    sc->err[slot * nb + tid] = bad ? NAN : 0.0;
+                    sc->bits[slot * nb + tid] = bad ? NAN : 0.0;
+                    if (!bad && sc->hist) sc->hist[slot * sc->hist_bins + sc->hoff[tid]] = (uint32_t)n;
+                }
+                if (bad && tid == 0) atomicOr(&p.status->nonfinite, 1u);
+                __syncthreads();
+                continue;
+            }
+
+            // ---- per-b scale and zero point (literal FP32 definition)
             if (tid < nb) {
-                sc->err[slot * nb + tid] = bad ? NAN : 0.0;
-                sc->bits[slot * nb + tid] = bad ? NAN : 0.0;
-                if (!bad && sc->hist) sc->hist[slot * sc->hist_bins + sc->hoff[tid]] = (uint32_t)n;
+                float P = ldexpf(1.0f, sc->bl[tid]);
+                float S = R / P;
+                float Z = 0.0f;
+                if (S != 0.0f) {
+                    float r = mx / S;
+                    Z = __builtin_rintf(P - r);
+                }
+                prmS[tid] = S;
+                prmZ[tid] = Z;
             }
-            if (bad && tid == 0) atomicOr(&p.status->nonfinite, 1u);
-            __syncthreads();
-            continue;
-        }
-
-        // ---- per-b scale and zero point (literal FP32 definition)
-        if (tid < nb) {
-            float P = ldexpf(1.0f, sc->bl[tid]);
-            float S = R / P;
-            float Z = 0.0f;
-            if (S != 0.0f) {
-                float r = mx / S;
-                Z = __builtin_rintf(P - r);
+            for (int i = tid; i < MGS_MAX_BITS * NW; i += NT) {
+                (&bitpart[0][0])[i] = 0.0;
+                (&errpart[0][0])[i] = 0.0;
             }
-            prmS[tid] = S;
-            prmZ[tid] = Z;
-        }
-        for (int i = tid; i < MGS_MAX_BITS * NW; i += NT) (&bitpart[0][0])[i] = 0.0;
-        const bool fast = R >= ldexpf(1.0f, sc->bmax - 126);
-        auto quotients = [&]() {
+            const bool fast = R >= ldexpf(1.0f, sc->bmax - 126);
+            // Fast tiles evaluate the loss on x * 2^-E with 2^E <= R < 2^(E+1)
+            // (R is normal here): every step S_b * 2^-E is then normal and near
+            // 2^-b, and the terms are rescaled by 2^(2E) in FP64.
+            const int E = fast ? (int)((__float_as_uint(R) >> 23) & 0xFFu) - 127 : 0;
+            const double esc = ldexp(1.0, 2 * E);
+            auto quotients = [&]() {
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) u[i] = fast ? (float)xd[i] / R : 0.0f;
-        };
-        quotients();
-        for (int i = tid; i < MGS_MAX_BITS * NW; i += NT) (&errpart[0][0])[i] = 0.0;
-        __syncthreads();
-
-        // ---- histogram batches
-        for (int bt = 0; bt < p.nbatches; ++bt) {
-            const int e0 = p.batch_begin[bt], e1 = p.batch_begin[bt + 1];
-            const int words = p.batch_words[bt];
-            for (int w = tid; w < words; w += NT) hist[w] = 0u;
+                for (int i = 0; i < EPT; ++i) {
+                    u[i] = fast ? xv[i] / R : 0.0f;
+                    xv[i] = ldexpf(xv[i], -E);
+                }
+            };
+            quotients();
             __syncthreads();
-            for (int ch = 0; ch < nchunk; ++ch) {
-                if constexpr (CHUNKED) {
-                    if (nchunk > 1) {
-                        gather(ch);
-                        quotients();
+
+            // ---- histogram batches
+            for (int bt = 0; bt < p.nbatches; ++bt) {
+                const int e0 = p.batch_begin[bt], e1 = p.batch_begin[bt + 1];
+                const int words = p.batch_words[bt];
+                {  // clear the batch's bins, 16 bytes per store
+                    uint4* h4 = reinterpret_cast<uint4*>(hist);
+                    for (int w = tid; w < (words >> 2); w += NT) h4[w] = make_uint4(0u, 0u, 0u, 0u);
+                    for (int w = (words & ~3) + tid; w < words; w += NT) hist[w] = 0u;
+                }
+                __syncthreads();
+                uint32_t ovf = 0;  // some bin grew past the LDS increment table
+                for (int ch = 0; ch < nchunk; ++ch) {
+                    if constexpr (CHUNKED) {
+                        if (nchunk > 1) {
+                            gather(ch);
+                            quotients();
+                        }
+                    }
+                    const int nc = min(CAP, n - ch * CAP);  // elements of this chunk
+                    const bool check = nc < CAP;
+                    for (int e = e0; e < e1; ++e) {
+                        const HistEntry en = p.entries[e];
+                        const int bi = en.bi;
+                        const float S = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmS[bi])));
+                        const float Z = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmZ[bi])));
+                        const float P = ldexpf(1.0f, sc->bl[bi]);
+                        const float Ss = ldexpf(S, -E);
+                        const int base = en.lds_off - en.lo;
+                        const int rl = en.rlog;
+                        const int cpy = lane & ((1 << rl) - 1);
+                        Part acc{0.0f, 0.0, 0.0};
+                        if (S == 0.0f) {
+                            // the range underflows at this b: every code is 0, xhat = min
+                            // (all counts go to bin 0: its entropy terms come from the scan)
+                            if (en.lo == 0 && tid == 0) hist[en.lds_off] += (uint32_t)nc;
+                            if (en.first) {
+#pragma unroll
+                                for (int i = 0; i < EPT; ++i) {
+                                    if (i * NT + tid < nc) {
+                                        double d = (double)mn - as_f64(xv[i]);
+                                        acc.err64 = __builtin_fma(as_f64(wv[i]), d * d, acc.err64);
+                                    }
+                                }
+                            }
+                        } else if (fast && !en.split && fabsf(Z) <= 8388608.0f) {
+                            if (en.packed)
+                                acc = eval_fast_dispatch<NT, EPT, true>(check, en.rtn, 0, 0, u, xv, wv, nc,
+                                                                        tid, P, Ss, Z, hist, base, lf, ovf);
+                            else
+                                acc = eval_fast_dispatch<NT, EPT, false>(check, en.rtn, rl, cpy, u, xv, wv,
+                                                                         nc, tid, P, Ss, Z, hist, base, lf,
+                                                                         ovf);
+                        } else {
+                            acc = eval_generic<NT, EPT>(u, xv, wv, nc, tid, P, S, Ss, Z, hist, base, en.lo,
+                                                        en.nwords, en.packed, rl, cpy, !fast, en.first,
+                                                        en.rtn, lf, ovf);
+                        }
+                        if (en.first) {
+                            const double tot = wave_total_f64((double)acc.err * esc + acc.err64);
+                            if (lane == 0) errpart[bi][wave] += tot;
+                        }
+                        if (en.rtn && S != 0.0f) {
+                            const double tot = wave_total_f64(acc.ent);
+                            if (lane == 0) bitpart[bi][wave] += tot;
+                        }
                     }
                 }
-                const int nc = min(CAP, n - ch * CAP);  // elements of this chunk
-                const bool check = nc < CAP;
+                const bool any_ovf = __syncthreads_or((int)ovf) != 0;
+                // ---- entropy terms of the scanned histograms, the corrections
+                // of incremental ones whose bins outgrew the LDS table (each such
+                // bin got T(LGTAB - 1) from the increments and needs T(h) on the
+                // same grid), and the optional debug copy of the bins
                 for (int e = e0; e < e1; ++e) {
                     const HistEntry en = p.entries[e];
-                    const int bi = en.bi;
-                    const float S = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmS[bi])));
-                    const float Z = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmZ[bi])));
-                    const float P = ldexpf(1.0f, sc->bl[bi]);
-                    const int base = en.lds_off - en.lo;
-                    double acc = 0.0;
-                    if (S == 0.0f) {
-                        // the range underflows at this b: every code is 0, xhat = min
-                        if (en.lo == 0 && tid == 0) hist[en.lds_off] += (uint32_t)nc;
-                        if (en.first) {
-#pragma unroll
-                            for (int i = 0; i < EPT; ++i) {
-                                if (i * NT + tid < nc) {
-                                    double d = (double)mn - as_f64(xd[i]);
-                                    acc = __builtin_fma(as_f64(wd[i]), d * d, acc);
+                    const bool scan = !en.rtn || prmS[en.bi] == 0.0f;
+                    const bool fix = !scan && any_ovf;
+                    uint32_t* hout = sc->hist ? sc->hist + slot * sc->hist_bins + sc->hoff[en.bi] : nullptr;
+                    if (!scan && !fix && !hout) continue;
+                    double s = 0.0;
+                    auto term = [&](uint32_t h) {
+                        if (scan) s += hlog2h(h, lg, lgt);
+                        else if (fix && h >= (uint32_t)(LGTAB - 1)) s += grid_round(lgt[h], p.kgrid) - rt_top;
+                    };
+                    if (en.rlog) {
+                        // replicated bins: the 2^rlog copies of a bin sit in adjacent
+                        // lanes of one wavefront; a butterfly sums them
+                        const int rl = en.rlog, R = 1 << rl;
+                        for (int w0 = 0; w0 < en.nwords; w0 += NT) {
+                            const int w = w0 + tid;
+                            uint32_t h = w < en.nwords ? hist[en.lds_off + w] : 0u;
+                            for (int o = 1; o < R; o <<= 1) h += (uint32_t)__shfl_xor((int)h, o, MGS_WAVE);
+                            if ((lane & (R - 1)) == 0 && w < en.nwords) {
+                                term(h);
+                                if (hout) hout[en.lo + (w >> rl)] = h;
+                            }
+                        }
+                    } else {
+                        for (int w = tid; w < en.nwords; w += NT) {
+                            uint32_t v = hist[en.lds_off + w];
+                            if (!en.packed) {
+                                term(v);
+                                if (hout) hout[en.lo + w] = v;
+                            } else {
+                                uint32_t h0 = v & 0xFFFFu, h1 = v >> 16;
+                                term(h0);
+                                term(h1);
+                                if (hout) {
+                                    hout[2 * (en.lo + w)] = h0;
+                                    hout[2 * (en.lo + w) + 1] = h1;
                                 }
                             }
                         }
-                    } else if (fast && !en.split && fabsf(Z) <= 8388608.0f) {
-                        if (en.packed)
-                            acc = eval_fast_dispatch<NT, EPT, XT, true>(check, en.first, u, xd, wd, nc, tid,
-                                                                    P, S, Z, hist, base);
-                        else
-                            acc = eval_fast_dispatch<NT, EPT, XT, false>(check, en.first, u, xd, wd, nc, tid,
-                                                                     P, S, Z, hist, base);
-                    } else {
-                        acc = eval_generic<NT, EPT, XT>(u, xd, wd, nc, tid, P, S, Z, hist, base, en.lo,
-                                                    en.nwords, en.packed, !fast, en.first);
                     }
-                    if (en.first) {
-                        acc = wave_sum_f64(acc);
-                        if (lane == 0) errpart[bi][wave] += acc;
+                    if (scan || fix) {
+                        const double tot = wave_total_f64(s);
+                        if (lane == 0) bitpart[en.bi][wave] += tot;
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
-            // ---- entropy terms (and the optional debug copy of the bins)
-            for (int e = e0; e < e1; ++e) {
-                const HistEntry en = p.entries[e];
-                double s = 0.0;
-                uint32_t* hout = sc->hist ? sc->hist + slot * sc->hist_bins + sc->hoff[en.bi] : nullptr;
-                for (int w = tid; w < en.nwords; w += NT) {
-                    uint32_t v = hist[en.lds_off + w];
-                    if (!en.packed) {
-                        s += hlog2h(v, lg, lgt);
-                        if (hout) hout[en.lo + w] = v;
-                    } else {
-                        uint32_t h0 = v & 0xFFFFu, h1 = v >> 16;
-                        s += hlog2h(h0, lg, lgt) + hlog2h(h1, lg, lgt);
-                        if (hout) {
-                            hout[2 * (en.lo + w)] = h0;
-                            hout[2 * (en.lo + w) + 1] = h1;
-                        }
-                    }
-                }
-                s = wave_sum_f64(s);
-                if (lane == 0) bitpart[en.bi][wave] += s;
-            }
-            __syncthreads();
-        }
 
-        // ---- finalize the tile's table entries
-        if (tid < nb) {
-            double e = 0.0, s = 0.0;
+            // ---- finalize the tile's table entries
+            if (tid < nb) {
+                double e = 0.0, s = 0.0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                e += errpart[tid][w];
-                s += bitpart[tid][w];
+                for (int w = 0; w < NW; ++w) {
+                    e += errpart[tid][w];
+                    s += bitpart[tid][w];
+                }
+                sc->err[slot * nb + tid] = e;
+                sc->bits[slot * nb + tid] = lgt[n] - s;  // n log2 n - sum_k h_k log2 h_k
             }
-            sc->err[slot * nb + tid] = e;
-            sc->bits[slot * nb + tid] = lgt[n] - s;
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -385,12 +523,18 @@ __global__ void scene_copy_kernel(SceneDesc sd, SceneDesc* dst) {
 // Empty slots (groups past ceil(k_t / G)) hold NaN; the debug histogram is
 // cleared; the status word is reset.
 __global__ void sweep_init_kernel(const SceneDesc* __restrict__ scenes, int count,
-                                  mgs_status_block* status, double* lgtab, int lgtab_max) {
+                                  mgs_status_block* status, double* lgtab, int lgtab_max, int K) {
     if (blockIdx.x == 0 && threadIdx.x == 0) status->nonfinite = 0u;
-    // h * log2(h) for every count a group can hold (FP64, 0 for h < 2)
+    // T(h) = h log2 h for every count a group can hold (FP64, 0 for h < 2),
+    // and the increments F[c] = R(T(c+1)) - R(T(c)) with R the rounding to the
+    // grid 2^-K: sums of increments telescope to R(T(h)) exactly, in any order
+    double* inc = lgtab + (lgtab_max + 1);
     for (int h = blockIdx.x * blockDim.x + threadIdx.x; h <= lgtab_max; h += gridDim.x * blockDim.x) {
-        double dh = (double)h;
-        lgtab[h] = h < 2 ? 0.0 : dh * log2(dh);
+        const double dh = (double)h, dh1 = (double)(h + 1);
+        const double t0 = h < 2 ? 0.0 : dh * log2(dh);
+        const double t1 = dh1 * log2(dh1);
+        lgtab[h] = t0;
+        inc[h] = grid_round(t1, K) - grid_round(t0, K);
     }
     for (int s = 0; s < count; ++s) {
         const SceneDesc* sc = &scenes[s];
@@ -444,7 +588,7 @@ static const Variant kVariants[] = {
     MGS_V(256, 1),  MGS_V(256, 2),  MGS_V(256, 4),  MGS_V(256, 8),  MGS_V(256, 16), MGS_V(256, 32),
     MGS_V(512, 1),  MGS_V(512, 2),  MGS_V(512, 4),  MGS_V(512, 8),  MGS_V(512, 16), MGS_V(512, 32),
     MGS_V(1024, 1), MGS_V(1024, 2), MGS_V(1024, 4), MGS_V(1024, 8), MGS_V(1024, 16),
-    MGS_VC(1024, 4),  // groups larger than any register-resident shape
+    MGS_VC(512, 16),  // groups larger than any register-resident shape
 };
 #undef MGS_V
 #undef MGS_VC
@@ -483,19 +627,26 @@ int device_cus() {
 // Static LDS of a kernel variant (everything but the histogram words).
 static int static_lds_bytes(int nt) {
     int nw = nt / MGS_WAVE;
-    return (int)(sizeof(double) * LGTAB + 2 * sizeof(double) * MGS_MAX_BITS * nw + 3 * 4 * nw +
+    return (int)(2 * sizeof(double) * LGTAB + 2 * sizeof(double) * MGS_MAX_BITS * nw + 3 * 4 * nw +
                  2 * 4 * MGS_MAX_BITS) + 256;
 }
 
-bool build_plan(const uint8_t* bl, int nb, int cap_words, SweepParams* p) {
+bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p) {
     // Greedy: largest histograms first, each into the first batch with room;
     // a b larger than a whole batch is split into windows of cap_words.
-    struct Item { int bi; int words; bool packed; };
+    // Scanned histograms with few bins get lane-interleaved copies (up to
+    // REPL_WORDS words) so that lanes landing in one bin do not serialise on
+    // one LDS address.
+    struct Item { int bi; int words; bool packed; int rlog; };
     std::vector<Item> items;
     for (int i = 0; i < nb; ++i) {
         int full = 1 << bl[i];
         bool packed = full > cap_words;
-        items.push_back({i, packed ? full / 2 : full, packed});
+        bool rtn = (int64_t)2 << bl[i] > G;
+        int rlog = 0;
+        if (!packed && !rtn)
+            while (rlog < REPL_MAX_LOG && (full << (rlog + 1)) <= std::min(REPL_WORDS, cap_words)) ++rlog;
+        items.push_back({i, packed ? full / 2 : full << rlog, packed, rlog});
     }
     std::stable_sort(items.begin(), items.end(),
                      [](const Item& a, const Item& c) { return a.words > c.words; });
@@ -509,6 +660,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, SweepParams* p) {
                 e.packed = it.packed;
                 e.first = lo == 0;
                 e.split = 1;
+                e.rtn = (int64_t)2 << bl[it.bi] > G;
                 e.lo = lo;
                 e.nwords = std::min(cap_words, it.words - lo);
                 e.lds_off = 0;
@@ -527,8 +679,12 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, SweepParams* p) {
         HistEntry e{};
         e.bi = (int16_t)it.bi;
         e.packed = it.packed;
+        e.rlog = (uint8_t)it.rlog;
         e.first = 1;
         e.split = 0;
+        // more bins than half the elements: the entropy comes from the atomics'
+        // old counts, which is cheaper than scanning mostly-empty bins
+        e.rtn = (int64_t)2 << bl[it.bi] > G;
         e.lo = 0;
         e.nwords = it.words;
         e.lds_off = used[k];
@@ -559,7 +715,7 @@ int plan_for(const SceneDesc& sc, const Shape& sh, SweepParams* p, size_t* lds_b
     // keep the capacity a power of two so bin windows tile 2^b evenly
     int pw = 1024;
     while (pw * 2 <= cap_words) pw *= 2;
-    if (!build_plan(sc.bl, sc.nb, pw, p)) return MGS_EINVAL;
+    if (!build_plan(sc.bl, sc.nb, pw, sc.G, p)) return MGS_EINVAL;
     *lds_bytes = (size_t)p->max_batch_words * 4;
     return MGS_OK;
 }
@@ -630,7 +786,7 @@ Shape default_shape(int G, int nb, int bmax) {
             if ((int64_t)t * e >= G && find_variant(t, e, G)) return Shape{t, e, 0};
         }
     }
-    return Shape{1024, 4, 0};  // chunked
+    return Shape{512, 16, 0};  // chunked
 }
 
 int launch_sweep(const SweepParams& p, const TileRef* tiles, const Shape& sh, size_t lds,
@@ -654,8 +810,15 @@ int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
     blocks = std::max<int64_t>(blocks, (lgtab_max + 256) / 256);
     blocks = std::min<int64_t>(blocks, 2048);
     hipLaunchKernelGGL(sweep_init_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_scenes, count,
-                       status, lgtab, lgtab_max);
+                       status, lgtab, lgtab_max, increment_grid_bits(lgtab_max));
     return mgs_last_launch();
+}
+
+int increment_grid_bits(int G) {
+    // largest total: sum over <= G elements of increments <= (G log2 G + G)
+    const double top = (double)G * std::log2((double)std::max(G, 2)) + (double)G + 1.0;
+    int bits = (int)std::ceil(std::log2(top));
+    return 52 - bits;
 }
 
 int max_resident_blocks(const Shape& sh, size_t lds, int G) {
@@ -700,7 +863,8 @@ void set_tuned_shape(int G, int nb, int bmax, const Shape& sh) {
 
 // ------------------------------------------------------------------ C ABI
 
-// Workspace: status word | scene descriptor | h log2 h table [0, G].
+// Workspace: status word | scene descriptor | h log2 h table [0, G] |
+// entropy increments [0, G].
 static size_t sweep_ws_scene_off() { return MGS_STATUS_BYTES; }
 static size_t sweep_ws_table_off() {
     return sweep_ws_scene_off() + mgs_align_up(sizeof(mgs::SceneDesc), 256);
@@ -709,22 +873,25 @@ static size_t sweep_ws_table_off() {
 extern "C" size_t mgs_quant_sweep_ws_bytes(const mgs_sweep_desc* desc) {
     int G = desc ? desc->G : MGS_MAX_GROUP;
     if (G < 1 || G > MGS_MAX_GROUP) G = MGS_MAX_GROUP;
-    return sweep_ws_table_off() + mgs_align_up(sizeof(double) * ((size_t)G + 1), 256);
+    return sweep_ws_table_off() + mgs_align_up(2 * sizeof(double) * ((size_t)G + 1), 256);
 }
 
-extern "C" int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
-                               const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
-                               float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes,
-                               void* stream) {
+// One sweep launch (init + kernel) with the registered, forced or default shape.
+static int sweep_launch(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                        const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                        float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes,
+                        hipStream_t s, const mgs::Shape* force) {
     using namespace mgs;
     SceneDesc sc;
     int rc = fill_scene(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, d_hist, &sc);
     if (rc) return rc;
     if (!d_ws || ws_bytes < mgs_quant_sweep_ws_bytes(desc)) return MGS_EWORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
     Shape sh;
-    if (!tuned_shape(sc.G, sc.nb, sc.bmax, &sh) || !shape_valid(sh, sc.G))
+    if (force) {
+        sh = *force;
+    } else if (!tuned_shape(sc.G, sc.nb, sc.bmax, &sh) || !shape_valid(sh, sc.G)) {
         sh = default_shape(sc.G, sc.nb, sc.bmax);
+    }
     if (!shape_valid(sh, sc.G)) return MGS_EINVAL;
     SweepParams p;
     std::memset(&p, 0, sizeof(p));
@@ -740,7 +907,121 @@ extern "C" int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, 
     p.scenes = d_sc;
     p.lgtab = lgtab;
     p.lgtab_max = sc.G;
-    p.ntiles = (int64_t)sc.C * sc.gpc;
+    p.kgrid = increment_grid_bits(sc.G);
+    p.cpb = sh.cpb > 0 ? std::min(sh.cpb, sc.C) : sc.C;
+    p.ntiles = (int64_t)((sc.C + p.cpb - 1) / p.cpb) * sc.gpc;
     if (p.ntiles == 0) return MGS_OK;
     return launch_sweep(p, nullptr, sh, lds, 0, s, sc.G);
+}
+
+extern "C" int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                               const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                               float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes,
+                               void* stream) {
+    return sweep_launch(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, d_hist, d_ws,
+                        ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+// Candidate shapes of the autotuner: kernel variants x LDS capacities x
+// channels per tile.
+static const int kLdsCaps[] = {0, 98304, 65536};
+static const int kCpbs[] = {0, 4, 2, 1};
+static constexpr int kNumCaps = (int)(sizeof(kLdsCaps) / sizeof(kLdsCaps[0]));
+static constexpr int kNumCpbs = (int)(sizeof(kCpbs) / sizeof(kCpbs[0]));
+
+extern "C" int mgs_sweep_shape_count(void) { return mgs::variant_count() * kNumCaps * kNumCpbs; }
+
+static mgs::Shape candidate_shape(int i) {
+    mgs::Shape sh = mgs::variant_shape(i / (kNumCaps * kNumCpbs));
+    sh.lds_cap = kLdsCaps[(i / kNumCpbs) % kNumCaps];
+    sh.cpb = kCpbs[i % kNumCpbs];
+    return sh;
+}
+
+extern "C" int mgs_sweep_set_shape(int32_t G, int32_t nb, int32_t bmax, int32_t nt, int32_t ept,
+                                   int32_t lds_cap, int32_t cpb) {
+    if (G < 1 || G > MGS_MAX_GROUP || nb < 1 || nb > MGS_MAX_BITS || bmax < 1 || bmax > MGS_MAX_BITS ||
+        cpb < 0)
+        return MGS_EINVAL;
+    mgs::Shape sh{nt, ept, lds_cap < 0 ? 0 : lds_cap, cpb};
+    if (nt != 0 && !mgs::shape_valid(sh, G)) return MGS_EINVAL;
+    mgs::set_tuned_shape(G, nb, bmax, sh);  // nt == 0 clears (falls back to the default)
+    return MGS_OK;
+}
+
+extern "C" int mgs_sweep_autotune(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                                  const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                                  float* d_gmax, void* d_ws, size_t ws_bytes, void* stream, int32_t reps,
+                                  float* h_ms, int32_t* h_shapes, int32_t* h_best) {
+    using namespace mgs;
+    SceneDesc sc;
+    int rc = fill_scene(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, nullptr, &sc);
+    if (rc) return rc;
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MGS_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MGS_EDEVICE;
+    }
+    const int n = mgs_sweep_shape_count();
+    float best_ms = -1.0f;
+    Shape best{0, 0, 0, 0};
+    int status = MGS_OK;
+    for (int i = 0; i < n && status == MGS_OK; ++i) {
+        Shape sh = candidate_shape(i);
+        if (h_shapes) {
+            h_shapes[4 * i] = sh.nt;
+            h_shapes[4 * i + 1] = sh.ept;
+            h_shapes[4 * i + 2] = sh.lds_cap;
+            h_shapes[4 * i + 3] = sh.cpb;
+        }
+        if (h_ms) h_ms[i] = -1.0f;
+        const int64_t capacity = (int64_t)sh.nt * sh.ept;
+        const bool chunked = variant_chunked(i / (kNumCaps * kNumCpbs));
+        if (chunked != (capacity < sc.G)) continue;
+        if (!chunked && capacity >= 4 * (int64_t)std::max(sc.G, 256)) continue;  // mostly idle lanes
+        if (!shape_valid(sh, sc.G)) continue;
+        rc = sweep_launch(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, nullptr, d_ws,
+                          ws_bytes, s, &sh);  // warm-up (and plan check)
+        if (rc == MGS_EINVAL) continue;       // plan does not fit this capacity
+        if (rc) {
+            status = rc;
+            break;
+        }
+        float tmin = 0.0f;
+        for (int r = 0; r < reps; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) status = MGS_EDEVICE;
+            rc = sweep_launch(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, nullptr, d_ws,
+                              ws_bytes, s, &sh);
+            if (rc) status = rc;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                status = MGS_EDEVICE;
+            float ms = 0.0f;
+            if (status == MGS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) status = MGS_EDEVICE;
+            if (status) break;
+            tmin = r == 0 ? ms : std::min(tmin, ms);
+        }
+        if (status) break;
+        if (h_ms) h_ms[i] = tmin;
+        if (best_ms < 0.0f || tmin < best_ms) {
+            best_ms = tmin;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status) return status;
+    if (best.nt == 0) return MGS_EINVAL;
+    set_tuned_shape(sc.G, sc.nb, sc.bmax, best);
+    if (h_best) {
+        h_best[0] = best.nt;
+        h_best[1] = best.ept;
+        h_best[2] = best.lds_cap;
+        h_best[3] = best.cpb;
+    }
+    // leave the tables as the chosen shape computes them
+    return sweep_launch(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, nullptr, d_ws,
+                        ws_bytes, s, &best);
 }

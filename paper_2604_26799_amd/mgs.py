@@ -43,6 +43,9 @@ SIGNATURES = {
     "mgs_prune_select": (ct.c_int, [P, I64, P, I32, P, P, SZ, P]),
     "mgs_quant_sweep_ws_bytes": (SZ, [P]),
     "mgs_quant_sweep": (ct.c_int, [P, P, P, P, P, P, P, P, P, P, SZ, P]),
+    "mgs_sweep_shape_count": (ct.c_int, []),
+    "mgs_sweep_autotune": (ct.c_int, [P, P, P, P, P, P, P, P, P, SZ, P, I32, P, P, P]),
+    "mgs_sweep_set_shape": (ct.c_int, [I32, I32, I32, I32, I32, I32, I32]),
     "mgs_quantize": (ct.c_int, [P, I64, I32, P, I64, I32, P, P, P, P, P]),
     "mgs_dequantize": (ct.c_int, [P, I64, I32, I32, P, P, P, P, P]),
     "mgs_vq_assign_ws_bytes": (SZ, [I64, I32, I32]),
@@ -176,6 +179,41 @@ def quant_sweep(attr, imp, kept, k, G: int, bits, want_hist: bool = False, ws=No
                                  _stream(stream)), "mgs_quant_sweep")
     _finish(ws, check, "mgs_quant_sweep", stream)
     return out
+
+
+def sweep_autotune(attr, imp, kept, k, G: int, bits, reps: int = 3, ws=None, out=None, stream=None):
+    """Time every launch shape of the sweep on these inputs and register the fastest.
+
+    Returns ``(best (nt, ept, lds_cap, cpb), [(nt, ept, lds_cap, cpb, ms), ...])``.
+    """
+    torch = _torch()
+    C, N = attr.shape
+    d = sweep_desc(N, C, k, G, bits)
+    T, nb = d.T, d.nb
+    gm = gmax_groups(k, G)
+    dev = attr.device
+    need = lib().mgs_quant_sweep_ws_bytes(ct.byref(d))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    if out is None:
+        out = {"err": torch.empty((T, C, gm, nb), dtype=torch.float64, device=dev),
+               "bits": torch.empty((T, C, gm, nb), dtype=torch.float64, device=dev),
+               "gmin": torch.empty((T, C, gm), dtype=torch.float32, device=dev),
+               "gmax": torch.empty((T, C, gm), dtype=torch.float32, device=dev)}
+    n = lib().mgs_sweep_shape_count()
+    ms = np.empty(n, dtype=np.float32)
+    shapes = np.empty((n, 4), dtype=np.int32)
+    best = np.empty(4, dtype=np.int32)
+    _check(lib().mgs_sweep_autotune(ct.byref(d), _dptr(attr), _dptr(imp), _dptr(kept), _dptr(out["err"]),
+                                    _dptr(out["bits"]), _dptr(out["gmin"]), _dptr(out["gmax"]), _dptr(ws),
+                                    ws.numel(), _stream(stream), reps, _np_ptr(ms), _np_ptr(shapes),
+                                    _np_ptr(best)), "mgs_sweep_autotune")
+    rows = [(int(a), int(b), int(c), int(d), float(m)) for (a, b, c, d), m in zip(shapes, ms) if m >= 0]
+    return tuple(int(v) for v in best), rows
+
+
+def sweep_set_shape(G: int, nb: int, bmax: int, nt: int, ept: int, lds_cap: int = 0, cpb: int = 0):
+    _check(lib().mgs_sweep_set_shape(G, nb, bmax, nt, ept, lds_cap, cpb), "mgs_sweep_set_shape")
 
 
 def quantize(attr, kept, G: int, bw, stream=None):

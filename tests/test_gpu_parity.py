@@ -1,9 +1,15 @@
 """HIP path vs the CPU oracle, element by element, through the C ABI.
 
 Bar: codes, histograms, kept indices and VQ indices bit-exact; loss and size
-tables within 1e-5 relative (the kernels evaluate every loss term exactly in
-FP64 and only the summation order differs, so the agreement is ~1e-13; the
-tests assert 1e-9, well inside the 1e-5 bar); group bounds equal as numbers.
+tables within 1e-5 relative.  On the fast path the kernels form each loss
+term in FP32 (on values scaled by an exact power of two) and sum up to EPT
+<= 32 of them per thread in FP32 before the FP64 reduction, so a group's loss
+carries a relative error of at most (32 + 3) * 2^-24 ~ 2.1e-6; the tests
+assert ERR_REL = 4e-6.  Literal-division and underflowed-step groups keep
+FP64 terms.  The size is the FP64 entropy; for bit-widths with more bins
+than half the group it comes from entropy increments on a 2^-K grid (exact
+sums), which adds an absolute error of at most G * 2^-(K+1) bits (K from
+increment_bits below); the tests assert 1e-9 relative plus that bound.
 """
 import math
 from fractions import Fraction
@@ -14,7 +20,8 @@ import pytest
 from paper_2604_26799_amd import mgs, synth
 
 pytestmark = pytest.mark.gpu
-REL = 1e-9
+ERR_REL = 4e-6
+BITS_REL = 1e-9
 
 
 @pytest.fixture(scope="module")
@@ -47,13 +54,20 @@ def gpu_sweep(torch, attr, imp, kept, k, G, bits, hist=True):
     return {key: (host(v) if v is not None else None) for key, v in out.items()}
 
 
-def assert_tables(got, want, hist=True):
+def increment_bits(G):
+    """Grid exponent of the entropy increments (kept in step with the library)."""
+    top = G * math.log2(max(G, 2)) + G + 1.0
+    return 52 - math.ceil(math.log2(top))
+
+
+def assert_tables(got, want, hist=True, G=None):
     assert got["err"].shape == want["err"].shape
+    atol_bits = 1e-9 if G is None else max(1e-9, G * 2.0 ** -(increment_bits(G) + 1))
     nan = np.isnan(want["err"])
     assert np.array_equal(np.isnan(got["err"]), nan)
     assert np.array_equal(np.isnan(got["bits"]), np.isnan(want["bits"]))
-    np.testing.assert_allclose(got["err"][~nan], want["err"][~nan], rtol=REL, atol=1e-300)
-    np.testing.assert_allclose(got["bits"][~nan], want["bits"][~nan], rtol=REL, atol=1e-9)
+    np.testing.assert_allclose(got["err"][~nan], want["err"][~nan], rtol=ERR_REL, atol=1e-300)
+    np.testing.assert_allclose(got["bits"][~nan], want["bits"][~nan], rtol=BITS_REL, atol=atol_bits)
     gn = ~np.isnan(want["gmin"])
     assert np.array_equal(got["gmin"][gn], want["gmin"][gn])
     assert np.array_equal(got["gmax"][gn], want["gmax"][gn])
@@ -70,7 +84,7 @@ def test_sweep_small_workload(torch, orc):
     kept = orc.prune_select(imp, k)
     want = orc.quant_sweep(attr, imp, kept, k, w.group, w.bits, want_hist=True)
     got = gpu_sweep(torch, attr, imp, kept, k, w.group, w.bits)
-    assert_tables(got, want)
+    assert_tables(got, want, G=w.group)
 
 
 @pytest.mark.parametrize("n,C,G,bits", [
@@ -92,7 +106,7 @@ def test_sweep_shapes(torch, orc, n, C, G, bits):
     hist = hist_fits(attr, k, G, bits)
     want = orc.quant_sweep(attr, imp, kept, k, G, bits, want_hist=hist)
     got = gpu_sweep(torch, attr, imp, kept, k, G, bits, hist=hist)
-    assert_tables(got, want, hist=hist)
+    assert_tables(got, want, hist=hist, G=G)
 
 
 def adversarial_scene(n, seed):
@@ -122,12 +136,52 @@ def test_sweep_adversarial(torch, orc, G):
     kept = orc.prune_select(imp, k)
     want = orc.quant_sweep(attr, imp, kept, k, G, bits, want_hist=False)
     got = gpu_sweep(torch, attr, imp, kept, k, G, bits, hist=False)
-    assert_tables(got, want, hist=False)
+    assert_tables(got, want, hist=False, G=G)
     # histograms of the adversarial channels at the small bit-widths
     hb = [1, 2, 7, 11]
     want = orc.quant_sweep(attr, imp, kept, k, G, hb, want_hist=True)
     got = gpu_sweep(torch, attr, imp, kept, k, G, hb, hist=True)
-    assert_tables(got, want, hist=True)
+    assert_tables(got, want, hist=True, G=G)
+
+
+def test_sweep_every_shape_identical(torch, orc):
+    """Launch shapes (threads, elements per thread, LDS capacity, channels per
+    tile, chunked) change nothing beyond the summation order of the loss:
+    every shape matches the oracle, shapes agree with each other within the
+    loss bound (sizes to 1e-12), group bounds exactly, and a repeated launch
+    of one shape is bit-identical."""
+    attr, imp = synth.scene(30000, 20, seed=9)
+    k = np.array([30000, 17777, 4097], np.int64)
+    G, bits = 4096, [2, 5, 9, 13, 16]
+    kept = orc.prune_select(imp, k)
+    want = orc.quant_sweep(attr, imp, kept, k, G, bits)
+    first = None
+    shapes = [(256, 16, 0, 0), (512, 8, 0, 1), (1024, 4, 65536, 3), (512, 16, 98304, 7),
+              (1024, 8, 0, 20), (256, 32, 65536, 2), (512, 16, 65536, 1)]
+    try:
+        for sh in shapes:
+            mgs.sweep_set_shape(G, len(bits), max(bits), *sh)
+            got = gpu_sweep(torch, attr, imp, kept, k, G, bits, hist=False)
+            assert_tables(got, want, hist=False, G=G)
+            again = gpu_sweep(torch, attr, imp, kept, k, G, bits, hist=False)
+            for key in ("err", "bits", "gmin", "gmax"):
+                assert np.array_equal(got[key], again[key], equal_nan=True), (sh, key)
+            if first is None:
+                first = got
+            else:
+                for key in ("gmin", "gmax"):
+                    assert np.array_equal(got[key], first[key], equal_nan=True), (sh, key)
+                ok = ~np.isnan(first["err"])
+                np.testing.assert_allclose(got["err"][ok], first["err"][ok], rtol=2 * ERR_REL)
+                np.testing.assert_allclose(got["bits"][ok], first["bits"][ok], rtol=1e-12, atol=1e-9)
+        # a group larger than the shape's capacity takes the chunked kernel
+        mgs.sweep_set_shape(16384, len(bits), max(bits), 512, 16, 0, 5)
+        want = orc.quant_sweep(attr, imp, kept, k, 16384, bits)
+        got = gpu_sweep(torch, attr, imp, kept, k, 16384, bits, hist=False)
+        assert_tables(got, want, hist=False, G=16384)
+    finally:
+        mgs.sweep_set_shape(G, len(bits), max(bits), 0, 0, 0, 0)
+        mgs.sweep_set_shape(16384, len(bits), max(bits), 0, 0, 0, 0)
 
 
 def test_sweep_nonfinite_flag(torch, orc):
@@ -150,8 +204,9 @@ def sampled_tiles(orc, attr, imp, kept, k, G, bits, got, picks):
         J = kept[offs[t]:offs[t + 1]][g * G:(g + 1) * G]
         sub = orc.quant_sweep(attr[c:c + 1, J], imp[J], np.arange(J.size, dtype=np.int32),
                               np.array([J.size]), G, bits)
-        np.testing.assert_allclose(got["err"][t, c, g], sub["err"][0, 0, 0], rtol=REL)
-        np.testing.assert_allclose(got["bits"][t, c, g], sub["bits"][0, 0, 0], rtol=REL, atol=1e-9)
+        np.testing.assert_allclose(got["err"][t, c, g], sub["err"][0, 0, 0], rtol=ERR_REL)
+        np.testing.assert_allclose(got["bits"][t, c, g], sub["bits"][0, 0, 0], rtol=BITS_REL,
+                                   atol=max(1e-9, G * 2.0 ** -(increment_bits(G) + 1)))
         assert got["gmin"][t, c, g] == sub["gmin"][0, 0, 0]
         assert got["gmax"][t, c, g] == sub["gmax"][0, 0, 0]
 
