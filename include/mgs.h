@@ -42,6 +42,7 @@ extern "C" {
 #define MGS_MAX_GROUP 65535   /* group size G (histogram counts are 16-bit) */
 #define MGS_MAX_BITS 16       /* candidate bit-widths are in [1, 16] */
 #define MGS_MAX_VQ_DIM 64     /* vector length of VQ assignment */
+#define MGS_MAX_JOBS 64       /* scenes in one multi-scene sweep launch */
 
 /* Text for a status code (static storage). */
 const char* mgs_strerror(int status);
@@ -90,8 +91,14 @@ int mgs_prune_select(const float* d_imp, int64_t n, const int64_t* h_k, int32_t 
  * Tables hold Gmax = ceil(max_t k_t / G) group slots per (t, c); slots past
  * ceil(k_t / G) are NaN.  d_hist (optional, may be NULL) receives the code
  * histograms, uint32 [T][C][Gmax][sum_i 2^bits[i]] (2^b bins per listed b,
- * in list order); meant for small inputs.  Codes and histograms are exact;
- * err and bits agree with an FP64 evaluation of the definitions to ~1e-12.
+ * in list order); meant for small inputs.  Codes, histograms and group
+ * bounds are exact.  err: each thread sums the FP32 terms of at most 32
+ * elements before an FP64 reduction, so it agrees with the FP64 definition
+ * within 35 * 2^-24 (~2.1e-6) relative (groups that need the literal
+ * division or whose step underflows keep FP64 terms).  bits: FP64 entropy,
+ * within ~1e-12 relative plus G * 2^-(K+1) absolute where the entropy comes
+ * from grid-rounded increments (K = 52 - ceil(log2(G log2 G + G + 1))).
+ * Results are deterministic: the same inputs give bit-identical tables.
  * Limits: 1 <= G <= MGS_MAX_GROUP, 1 <= T <= MGS_MAX_RATIOS, h_bits strictly
  * increasing in [1, 16], ld >= N, 0 <= k_t <= N, kept indices in [0, N).
  * Errors: MGS_EINVAL, MGS_EWORKSPACE; non-finite attributes or weights in a
@@ -113,6 +120,32 @@ size_t mgs_quant_sweep_ws_bytes(const mgs_sweep_desc* desc);
 int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
                     const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
                     float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Batched sweep: the sweeps of up to MGS_MAX_JOBS scenes (each with its own
+ * N, C, reserve ratios, inputs and tables, all sharing G and the bit-width
+ * list) in one launch; every table equals what mgs_quant_sweep computes for
+ * that scene alone, bit for bit.  h_jobs (host, njobs entries) is read
+ * during the call only.  The workspace (mgs_quant_sweep_multi_ws_bytes,
+ * which depends on njobs and G) carries one status word for the whole
+ * launch.  Errors: as mgs_quant_sweep, plus MGS_EINVAL when njobs is outside
+ * [1, MGS_MAX_JOBS] or the jobs differ in G or the bit-width list.
+ */
+typedef struct {
+    mgs_sweep_desc desc;
+    const float* d_attr;    /* [C][ld] */
+    const float* d_imp;     /* [N] */
+    const int32_t* d_kept;  /* [sum_t k_t] */
+    double* d_err;          /* [T][C][Gmax][nb] */
+    double* d_bits;         /* [T][C][Gmax][nb] */
+    float* d_gmin;          /* [T][C][Gmax] */
+    float* d_gmax;          /* [T][C][Gmax] */
+    uint32_t* d_hist;       /* optional, as in mgs_quant_sweep */
+} mgs_sweep_job;
+
+size_t mgs_quant_sweep_multi_ws_bytes(const mgs_sweep_job* h_jobs, int32_t njobs);
+int mgs_quant_sweep_multi(const mgs_sweep_job* h_jobs, int32_t njobs, void* d_ws, size_t ws_bytes,
+                          void* stream);
 
 /*
  * Launch shape of the sweep kernel (threads per workgroup, elements per
@@ -175,6 +208,24 @@ size_t mgs_vq_assign_ws_bytes(int64_t N, int32_t D, int32_t K);
 int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float* d_cb, int32_t K,
                   int32_t* d_idx, double* d_dist, int64_t* d_nfallback, void* d_ws,
                   size_t ws_bytes, void* stream);
+
+/* ======================================================================
+ * Replayable launch sequences (hipGraph).
+ *
+ * mgs_graph_begin starts capturing `stream` (which must not be the legacy
+ * default stream); the mgs_* device calls that follow on it are recorded
+ * instead of run (host-side argument checks still run at capture time);
+ * mgs_graph_end ends the capture and returns an executable graph in
+ * *h_graph, which mgs_graph_launch replays on any stream with the same
+ * pointers and sizes (buffer contents may change between replays) and
+ * mgs_graph_destroy frees.  Calls that synchronise (mgs_status_fetch,
+ * mgs_sweep_autotune) must not be captured.  Errors: MGS_EINVAL (NULL
+ * stream or handle), MGS_EDEVICE (the runtime refused the capture).
+ * ====================================================================== */
+int mgs_graph_begin(void* stream);
+int mgs_graph_end(void* stream, void** h_graph);
+int mgs_graph_launch(void* graph, void* stream);
+int mgs_graph_destroy(void* graph);
 
 /* ======================================================================
  * Host side of the search (CPU).

@@ -22,6 +22,7 @@ OUT = os.path.join(HERE, "libmgs.so")
 ROOT = os.path.dirname(HERE)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_INC = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "include")
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include")]
@@ -35,7 +36,9 @@ def _compile(src: str, verbose: bool) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, "-c", "-x", "hip", *COMMON, *DEVICE, src, "-o", obj]
     else:
-        cmd = [HIPCC, "-c", *COMMON, "-fopenmp", src, "-o", obj]
+        # host-only C++ (no device pass): the HIP runtime API from its headers
+        cmd = [HIPCC, "-c", "-x", "c++", *COMMON, "-I", ROCM_INC, "-D__HIP_PLATFORM_AMD__", "-fopenmp",
+               src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

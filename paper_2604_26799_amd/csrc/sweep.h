@@ -49,15 +49,6 @@ struct SceneDesc {
     uint8_t bl[MGS_MAX_BITS];
 };
 
-// A tile of a multi-scene work list: ratio t, group g, channels
-// [c, min(C, c + cpb)).
-struct TileRef {
-    int32_t scene;
-    int32_t t;
-    int32_t c;
-    int32_t g;
-};
-
 // Kernel arguments shared by all tiles of one launch.
 struct SweepParams {
     mgs_status_block* status;
@@ -65,6 +56,8 @@ struct SweepParams {
     const double* lgtab;      // T(h) = h log2 h for h in [0, lgtab_max], then the increments
                               // F[c] = R(T(c+1)) - R(T(c)), R: rounding to the grid 2^-K
     int64_t ntiles;
+    int64_t tcum[MGS_MAX_JOBS + 1];  // prefix of the tiles of each scene
+    int32_t nscenes;
     int32_t lgtab_max;
     int32_t cpb;              // channels per tile
     int32_t nbatches, nentries, max_batch_words;
@@ -97,7 +90,7 @@ int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
 int increment_grid_bits(int G);
 // G: the largest group size of the launch (selects the chunked kernel when
 // it exceeds the shape's nt * ept).
-int launch_sweep(const SweepParams& p, const TileRef* tiles, const Shape& sh, size_t lds,
+int launch_sweep(const SweepParams& p, const Shape& sh, size_t lds,
                  int64_t grid, hipStream_t s, int G);
 int max_resident_blocks(const Shape& sh, size_t lds, int G);
 int device_cus();

@@ -216,7 +216,7 @@ constexpr int sweep_min_waves() { return (EPT <= 16 && !CHUNKED) ? 4 : 1; }
 
 template <int NT, int EPT, bool CHUNKED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<NT, EPT, CHUNKED>())))
-void sweep_kernel(SweepParams p, const TileRef* __restrict__ tiles) {
+void sweep_kernel(SweepParams p) {
     constexpr int NW = NT / MGS_WAVE;
     extern __shared__ uint32_t hist[];
     __shared__ double lg[LGTAB];
@@ -241,20 +241,17 @@ void sweep_kernel(SweepParams p, const TileRef* __restrict__ tiles) {
     const double rt_top = grid_round(lgt[min(LGTAB - 1, p.lgtab_max)], p.kgrid);
 
     for (int64_t it = blockIdx.x; it < p.ntiles; it += gridDim.x) {
-        // ---- locate the tile: (ratio t, group g) for channels [c0, c1)
+        // ---- locate the tile: scene, then (channel run, ratio t, group g);
+        // channels [c0, c1)
+        int sid = 0;
+        while (sid + 1 < p.nscenes && p.tcum[sid + 1] <= it) ++sid;
+        const SceneDesc* sc = &p.scenes[sid];
         int t, c0, g;
-        const SceneDesc* sc;
-        if (tiles) {
-            TileRef tr = tiles[it];
-            sc = &p.scenes[tr.scene];
-            t = tr.t;
-            c0 = tr.c;
-            g = tr.g;
-        } else {
-            sc = &p.scenes[0];
+        {
+            const int64_t lt = it - p.tcum[sid];
             const int64_t gpc = sc->gpc;
-            const int cc = (int)(it / gpc);
-            const int r = (int)(it - (int64_t)cc * gpc);
+            const int cc = (int)(lt / gpc);
+            const int r = (int)(lt - (int64_t)cc * gpc);
             c0 = cc * p.cpb;
             t = 0;
             while (t + 1 < sc->T && sc->gcum[t + 1] <= r) ++t;
@@ -561,22 +558,21 @@ __global__ void sweep_init_kernel(const SceneDesc* __restrict__ scenes, int coun
 // ------------------------------------------------------------------ host side
 
 template <int NT, int EPT, bool CHUNKED>
-static hipError_t launch_one(const SweepParams& p, const TileRef* tiles, int64_t grid, size_t lds,
+static hipError_t launch_one(const SweepParams& p, int64_t grid, size_t lds,
                              hipStream_t s) {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel<NT, EPT, CHUNKED>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)e;
     }
-    hipLaunchKernelGGL((sweep_kernel<NT, EPT, CHUNKED>), dim3((unsigned)grid), dim3(NT), lds, s, p,
-                       tiles);
+    hipLaunchKernelGGL((sweep_kernel<NT, EPT, CHUNKED>), dim3((unsigned)grid), dim3(NT), lds, s, p);
     return hipGetLastError();
 }
 
 struct Variant {
     int nt, ept;
     bool chunked;
-    hipError_t (*fn)(const SweepParams&, const TileRef*, int64_t, size_t, hipStream_t);
+    hipError_t (*fn)(const SweepParams&, int64_t, size_t, hipStream_t);
     const void* kern;
 };
 
@@ -789,14 +785,14 @@ Shape default_shape(int G, int nb, int bmax) {
     return Shape{512, 16, 0};  // chunked
 }
 
-int launch_sweep(const SweepParams& p, const TileRef* tiles, const Shape& sh, size_t lds,
+int launch_sweep(const SweepParams& p, const Shape& sh, size_t lds,
                  int64_t grid, hipStream_t s, int G) {
     const Variant* v = find_variant(sh.nt, sh.ept, G);
     if (!v) return MGS_EINVAL;
     if (grid <= 0 || grid > p.ntiles) grid = p.ntiles;
     if (grid < 1) return MGS_OK;
     if (grid > 0x7fffffff) grid = 0x7fffffff;
-    return v->fn(p, tiles, grid, lds, s) == hipSuccess ? MGS_OK : MGS_EDEVICE;
+    return v->fn(p, grid, lds, s) == hipSuccess ? MGS_OK : MGS_EDEVICE;
 }
 
 int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
@@ -865,53 +861,80 @@ void set_tuned_shape(int G, int nb, int bmax, const Shape& sh) {
 
 // Workspace: status word | scene descriptor | h log2 h table [0, G] |
 // entropy increments [0, G].
+// Workspace: status word | scene descriptors | h log2 h table [0, G] |
+// entropy increments [0, G].
 static size_t sweep_ws_scene_off() { return MGS_STATUS_BYTES; }
-static size_t sweep_ws_table_off() {
-    return sweep_ws_scene_off() + mgs_align_up(sizeof(mgs::SceneDesc), 256);
+static size_t sweep_ws_table_off(int nscenes) {
+    return sweep_ws_scene_off() + mgs_align_up(sizeof(mgs::SceneDesc) * (size_t)nscenes, 256);
+}
+static size_t sweep_ws_bytes(int nscenes, int G) {
+    if (G < 1 || G > MGS_MAX_GROUP) G = MGS_MAX_GROUP;
+    return sweep_ws_table_off(nscenes) + mgs_align_up(2 * sizeof(double) * ((size_t)G + 1), 256);
 }
 
 extern "C" size_t mgs_quant_sweep_ws_bytes(const mgs_sweep_desc* desc) {
-    int G = desc ? desc->G : MGS_MAX_GROUP;
-    if (G < 1 || G > MGS_MAX_GROUP) G = MGS_MAX_GROUP;
-    return sweep_ws_table_off() + mgs_align_up(2 * sizeof(double) * ((size_t)G + 1), 256);
+    return sweep_ws_bytes(1, desc ? desc->G : MGS_MAX_GROUP);
 }
 
-// One sweep launch (init + kernel) with the registered, forced or default shape.
-static int sweep_launch(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
-                        const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
-                        float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes,
-                        hipStream_t s, const mgs::Shape* force) {
+extern "C" size_t mgs_quant_sweep_multi_ws_bytes(const mgs_sweep_job* h_jobs, int32_t njobs) {
+    if (!h_jobs || njobs < 1 || njobs > MGS_MAX_JOBS) return sweep_ws_bytes(MGS_MAX_JOBS, MGS_MAX_GROUP);
+    return sweep_ws_bytes(njobs, h_jobs[0].desc.G);
+}
+
+// One launch over the tiles of `n` scenes that share G and the bit list.
+static int sweep_launch_scenes(const mgs::SceneDesc* scs, int n, void* d_ws, size_t ws_bytes,
+                               hipStream_t s, const mgs::Shape* force) {
     using namespace mgs;
-    SceneDesc sc;
-    int rc = fill_scene(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, d_hist, &sc);
-    if (rc) return rc;
-    if (!d_ws || ws_bytes < mgs_quant_sweep_ws_bytes(desc)) return MGS_EWORKSPACE;
+    if (n < 1 || n > MGS_MAX_JOBS) return MGS_EINVAL;
+    const SceneDesc& s0 = scs[0];
+    for (int i = 1; i < n; ++i) {
+        if (scs[i].G != s0.G || scs[i].nb != s0.nb) return MGS_EINVAL;
+        for (int b = 0; b < s0.nb; ++b)
+            if (scs[i].bl[b] != s0.bl[b]) return MGS_EINVAL;
+    }
+    if (!d_ws || ws_bytes < sweep_ws_bytes(n, s0.G)) return MGS_EWORKSPACE;
     Shape sh;
     if (force) {
         sh = *force;
-    } else if (!tuned_shape(sc.G, sc.nb, sc.bmax, &sh) || !shape_valid(sh, sc.G)) {
-        sh = default_shape(sc.G, sc.nb, sc.bmax);
+    } else if (!tuned_shape(s0.G, s0.nb, s0.bmax, &sh) || !shape_valid(sh, s0.G)) {
+        sh = default_shape(s0.G, s0.nb, s0.bmax);
     }
-    if (!shape_valid(sh, sc.G)) return MGS_EINVAL;
+    if (!shape_valid(sh, s0.G)) return MGS_EINVAL;
     SweepParams p;
     std::memset(&p, 0, sizeof(p));
     size_t lds = 0;
-    rc = plan_for(sc, sh, &p, &lds);
+    int rc = plan_for(s0, sh, &p, &lds);
     if (rc) return rc;
+    int cmax = 1;
+    for (int i = 0; i < n; ++i) cmax = std::max(cmax, (int)scs[i].C);
+    p.cpb = sh.cpb > 0 ? sh.cpb : cmax;
+    p.nscenes = n;
+    p.tcum[0] = 0;
+    for (int i = 0; i < n; ++i)
+        p.tcum[i + 1] = p.tcum[i] + (int64_t)((scs[i].C + p.cpb - 1) / p.cpb) * scs[i].gpc;
+    p.ntiles = p.tcum[n];
     auto* status = (mgs_status_block*)d_ws;
     auto* d_sc = (SceneDesc*)((char*)d_ws + sweep_ws_scene_off());
-    auto* lgtab = (double*)((char*)d_ws + sweep_ws_table_off());
-    rc = launch_init(&sc, 1, d_sc, status, lgtab, sc.G, s);
+    auto* lgtab = (double*)((char*)d_ws + sweep_ws_table_off(n));
+    rc = launch_init(scs, n, d_sc, status, lgtab, s0.G, s);
     if (rc) return rc;
     p.status = status;
     p.scenes = d_sc;
     p.lgtab = lgtab;
-    p.lgtab_max = sc.G;
-    p.kgrid = increment_grid_bits(sc.G);
-    p.cpb = sh.cpb > 0 ? std::min(sh.cpb, sc.C) : sc.C;
-    p.ntiles = (int64_t)((sc.C + p.cpb - 1) / p.cpb) * sc.gpc;
+    p.lgtab_max = s0.G;
+    p.kgrid = increment_grid_bits(s0.G);
     if (p.ntiles == 0) return MGS_OK;
-    return launch_sweep(p, nullptr, sh, lds, 0, s, sc.G);
+    return launch_sweep(p, sh, lds, 0, s, s0.G);
+}
+
+static int sweep_launch(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                        const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                        float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes,
+                        hipStream_t s, const mgs::Shape* force) {
+    mgs::SceneDesc sc;
+    int rc = mgs::fill_scene(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, d_hist, &sc);
+    if (rc) return rc;
+    return sweep_launch_scenes(&sc, 1, d_ws, ws_bytes, s, force);
 }
 
 extern "C" int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
@@ -920,6 +943,19 @@ extern "C" int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, 
                                void* stream) {
     return sweep_launch(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, d_hist, d_ws,
                         ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+extern "C" int mgs_quant_sweep_multi(const mgs_sweep_job* h_jobs, int32_t njobs, void* d_ws,
+                                     size_t ws_bytes, void* stream) {
+    if (!h_jobs || njobs < 1 || njobs > MGS_MAX_JOBS) return MGS_EINVAL;
+    std::vector<mgs::SceneDesc> scs((size_t)njobs);
+    for (int i = 0; i < njobs; ++i) {
+        const mgs_sweep_job& j = h_jobs[i];
+        int rc = mgs::fill_scene(&j.desc, j.d_attr, j.d_imp, j.d_kept, j.d_err, j.d_bits, j.d_gmin,
+                                 j.d_gmax, j.d_hist, &scs[(size_t)i]);
+        if (rc) return rc;
+    }
+    return sweep_launch_scenes(scs.data(), njobs, d_ws, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 // Candidate shapes of the autotuner: kernel variants x LDS capacities x

@@ -44,7 +44,6 @@ constexpr int VQ_ROWSETS = 2;                          // 32-row sets per wave
 constexpr int VQ_ROWS = VQ_WAVES * VQ_ROWSETS * 32;    // rows per workgroup
 constexpr int VQ_CHUNK = 256;                          // codewords per LDS chunk
 constexpr int VQ_CAND = 12;                            // candidate slots per lane and row set
-constexpr int VQ_KS_MAX = 5;                           // 16-wide K steps (D + 2 <= 80)
 
 struct VqArgs {
     const float* x;

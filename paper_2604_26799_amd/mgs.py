@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmgs.so")
 
 OK, EINVAL, ENONFINITE, EINFEASIBLE, EDEVICE, EWORKSPACE, ELIMIT = 0, -1, -2, -3, -4, -5, -6
-MAX_RATIOS, MAX_GROUP, MAX_BITS, MAX_VQ_DIM = 64, 65535, 16, 64
+MAX_RATIOS, MAX_GROUP, MAX_BITS, MAX_VQ_DIM, MAX_JOBS = 64, 65535, 16, 64, 64
 
 _lib = None
 
@@ -33,6 +33,12 @@ class SweepDesc(ct.Structure):
                 ("G", ct.c_int32), ("nb", ct.c_int32), ("h_k", ct.c_void_p), ("h_bits", ct.c_void_p)]
 
 
+class SweepJob(ct.Structure):
+    _fields_ = [("desc", SweepDesc), ("d_attr", ct.c_void_p), ("d_imp", ct.c_void_p), ("d_kept", ct.c_void_p),
+                ("d_err", ct.c_void_p), ("d_bits", ct.c_void_p), ("d_gmin", ct.c_void_p),
+                ("d_gmax", ct.c_void_p), ("d_hist", ct.c_void_p)]
+
+
 # name -> (restype, argtypes); the full exported surface of include/mgs.h
 P, I32, I64, SZ, D = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t, ct.c_double
 SIGNATURES = {
@@ -43,6 +49,8 @@ SIGNATURES = {
     "mgs_prune_select": (ct.c_int, [P, I64, P, I32, P, P, SZ, P]),
     "mgs_quant_sweep_ws_bytes": (SZ, [P]),
     "mgs_quant_sweep": (ct.c_int, [P, P, P, P, P, P, P, P, P, P, SZ, P]),
+    "mgs_quant_sweep_multi_ws_bytes": (SZ, [P, I32]),
+    "mgs_quant_sweep_multi": (ct.c_int, [P, I32, P, SZ, P]),
     "mgs_sweep_shape_count": (ct.c_int, []),
     "mgs_sweep_autotune": (ct.c_int, [P, P, P, P, P, P, P, P, P, SZ, P, I32, P, P, P]),
     "mgs_sweep_set_shape": (ct.c_int, [I32, I32, I32, I32, I32, I32, I32]),
@@ -50,6 +58,10 @@ SIGNATURES = {
     "mgs_dequantize": (ct.c_int, [P, I64, I32, I32, P, P, P, P, P]),
     "mgs_vq_assign_ws_bytes": (SZ, [I64, I32, I32]),
     "mgs_vq_assign": (ct.c_int, [P, I64, I32, P, I32, P, P, P, P, SZ, P]),
+    "mgs_graph_begin": (ct.c_int, [P]),
+    "mgs_graph_end": (ct.c_int, [P, ct.POINTER(ct.c_void_p)]),
+    "mgs_graph_launch": (ct.c_int, [P, P]),
+    "mgs_graph_destroy": (ct.c_int, [P]),
     "mgs_ilp_solve": (ct.c_int, [P, P, I64, I32, I64, P, P, P]),
     "mgs_size_table": (ct.c_int, [P, P, I64, I32, P, I32, P]),
     "mgs_search": (ct.c_int, [P, P, P, I64, I32, I32, I32, P, P, P, P, P]),
@@ -179,6 +191,103 @@ def quant_sweep(attr, imp, kept, k, G: int, bits, want_hist: bool = False, ws=No
                                  _stream(stream)), "mgs_quant_sweep")
     _finish(ws, check, "mgs_quant_sweep", stream)
     return out
+
+
+def sweep_tables(T: int, C: int, gm: int, nb: int, device, hist_bins: int = 0):
+    """Empty output tables of one scene's sweep."""
+    torch = _torch()
+    out = {"err": torch.empty((T, C, gm, nb), dtype=torch.float64, device=device),
+           "bits": torch.empty((T, C, gm, nb), dtype=torch.float64, device=device),
+           "gmin": torch.empty((T, C, gm), dtype=torch.float32, device=device),
+           "gmax": torch.empty((T, C, gm), dtype=torch.float32, device=device),
+           "hist": None}
+    if hist_bins:
+        out["hist"] = torch.empty((T, C, gm, hist_bins), dtype=torch.int32, device=device)
+    return out
+
+
+def sweep_jobs(scenes, G: int, bits, want_hist: bool = False):
+    """Job array of a batched sweep.
+
+    ``scenes``: sequence of dicts with ``attr [C][N]`` (or ``[C][ld]`` with ``n``), ``imp``, ``kept``,
+    ``k`` and optionally ``out`` (tables, else allocated).  Returns ``(jobs, outs)``.
+    """
+    n = len(scenes)
+    jobs = (SweepJob * n)()
+    outs, keep = [], []
+    for i, sc in enumerate(scenes):
+        attr, imp, kept, k = sc["attr"], sc["imp"], sc["kept"], sc["k"]
+        C, ld = attr.shape
+        N = int(sc.get("n", ld))
+        d = sweep_desc(N, C, k, G, bits, ld=ld)
+        gm = gmax_groups(k, G)
+        hb = int(sum(1 << int(b) for b in d._keep[1])) if want_hist else 0
+        out = sc.get("out") or sweep_tables(d.T, C, gm, d.nb, attr.device, hb)
+        jobs[i].desc = d
+        jobs[i].d_attr = _dptr(attr)
+        jobs[i].d_imp = _dptr(imp)
+        jobs[i].d_kept = _dptr(kept) if kept.numel() else None
+        for key in ("err", "bits", "gmin", "gmax", "hist"):
+            setattr(jobs[i], "d_" + key, _dptr(out[key]))
+        outs.append(out)
+        keep.append(d)
+    jobs._keep = keep  # host arrays referenced by the descriptors
+    return jobs, outs
+
+
+def quant_sweep_multi(scenes, G: int, bits, want_hist: bool = False, ws=None, stream=None, check: bool = True,
+                      jobs=None):
+    """Batched sweep of several scenes in one launch; returns one table dict per scene."""
+    if jobs is None:
+        jobs, outs = sweep_jobs(scenes, G, bits, want_hist)
+    else:
+        outs = None
+    n = len(jobs)
+    need = lib().mgs_quant_sweep_multi_ws_bytes(jobs, n)
+    if ws is None or ws.numel() < need:
+        dev = scenes[0]["attr"].device
+        ws = workspace(need, dev)
+    _check(lib().mgs_quant_sweep_multi(jobs, n, _dptr(ws), ws.numel(), _stream(stream)), "mgs_quant_sweep_multi")
+    _finish(ws, check, "mgs_quant_sweep_multi", stream)
+    return outs
+
+
+class Graph:
+    """A captured sequence of library calls, replayed with ``launch``."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def launch(self, stream=None):
+        _check(lib().mgs_graph_launch(self.handle, _stream(stream)), "mgs_graph_launch")
+
+    def close(self):
+        if self.handle:
+            _check(lib().mgs_graph_destroy(self.handle), "mgs_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture(fn, stream):
+    """Record the library calls ``fn()`` makes on ``stream`` (not the default stream) into a Graph."""
+    sp = _stream(stream)
+    _check(lib().mgs_graph_begin(sp), "mgs_graph_begin")
+    try:
+        fn()
+    except BaseException:
+        h = ct.c_void_p()
+        lib().mgs_graph_end(sp, ct.byref(h))
+        if h.value:
+            lib().mgs_graph_destroy(h)
+        raise
+    h = ct.c_void_p()
+    _check(lib().mgs_graph_end(sp, ct.byref(h)), "mgs_graph_end")
+    return Graph(h.value)
 
 
 def sweep_autotune(attr, imp, kept, k, G: int, bits, reps: int = 3, ws=None, out=None, stream=None):

@@ -62,6 +62,39 @@ def test_sweep_rejects_bad_descriptors():
                              None) == mgs.EINVAL
 
 
+def test_multi_sweep_rejects_bad_job_lists():
+    L = mgs.lib()
+    fake = 0x1000
+    jobs = (mgs.SweepJob * 2)()
+    keep = []
+    for i, G in enumerate((16, 32)):
+        d = mgs.sweep_desc(100, 2, [50], G, [2, 4])
+        keep.append(d)
+        jobs[i].desc = d
+        for f in ("d_attr", "d_imp", "d_kept", "d_err", "d_bits", "d_gmin", "d_gmax"):
+            setattr(jobs[i], f, fake)
+    ws = ct.c_void_p(fake)
+    assert L.mgs_quant_sweep_multi(jobs, 0, ws, 1 << 30, None) == mgs.EINVAL
+    assert L.mgs_quant_sweep_multi(jobs, 65, ws, 1 << 30, None) == mgs.EINVAL
+    assert L.mgs_quant_sweep_multi(None, 1, ws, 1 << 30, None) == mgs.EINVAL
+    assert L.mgs_quant_sweep_multi(jobs, 2, ws, 1 << 30, None) == mgs.EINVAL   # G differs
+    jobs[1].desc = keep[0]
+    jobs[1].d_err = None
+    assert L.mgs_quant_sweep_multi(jobs, 2, ws, 1 << 30, None) == mgs.EINVAL   # missing table
+    jobs[1].d_err = fake
+    assert L.mgs_quant_sweep_multi(jobs, 2, None, 0, None) == mgs.EWORKSPACE
+    assert L.mgs_quant_sweep_multi_ws_bytes(jobs, 2) > L.mgs_quant_sweep_multi_ws_bytes(jobs, 1) > 0
+
+
+def test_graph_calls_reject_null_handles():
+    L = mgs.lib()
+    h = ct.c_void_p()
+    assert L.mgs_graph_begin(None) == mgs.EINVAL
+    assert L.mgs_graph_end(None, ct.byref(h)) == mgs.EINVAL
+    assert L.mgs_graph_launch(None, None) == mgs.EINVAL
+    assert L.mgs_graph_destroy(None) == mgs.EINVAL
+
+
 def test_other_entry_points_reject_bad_arguments():
     L = mgs.lib()
     fake = ct.c_void_p(0x1000)
