@@ -56,6 +56,8 @@ def parse():
                     help="only run a plain device-to-device copy of MIB MiB five times (counter calibration)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-candidate comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=64,
+                    help="jobs of the served stream (Poisson 2/s); 0 skips the served form")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time of the CPU baseline")
     return ap.parse_args()
 
@@ -267,6 +269,10 @@ def main():
     }
     if not args.no_plain:
         out["plain_per_candidate"] = plain_sweep(mgs, torch, attr, imp, kept, k, G, w.bits, s, med["sweep"])
+    if args.serve_jobs > 0:
+        del attr, imp, sh, cb, kept, tab, recon, codes, ws_v
+        torch.cuda.empty_cache()
+        out["serving"] = served_stream(args.serve_jobs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, attr_h, imp_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -294,6 +300,25 @@ def plain_sweep(mgs, torch, attr, imp, kept, k, G, bits, s, batched_ms):
         best = ms if best is None else min(best, ms)
     return {"launches": len(k) * len(bits), "ms": best, "batched_ms": batched_ms,
             "speedup_batched": best / batched_ms}
+
+
+def served_stream(num_jobs):
+    """The serving stream (Poisson arrivals at 2 jobs/s, N log-uniform in
+    [2e5, 6e6], 20 channels, 16 ratios x b in 2..16, budget raw/U(10, 60)),
+    served with continuous batching and, for comparison, one job at a time
+    with one launch per candidate."""
+    from paper_2604_26799_amd import serve, synth
+    store = serve.SceneStore()
+    jobs = synth.job_stream(num_jobs, 2.0, seed=0)
+    res = {"jobs": num_jobs, "arrivals_per_s": 2.0}
+    for mode in ("batched", "plain"):
+        srv = serve.Server(store, mode=mode)
+        r = srv.run(jobs)
+        srv.close()
+        print(f"served {mode}: p50 {r['p50_s']:.3f} s, p99 {r['p99_s']:.3f} s, "
+              f"{r['evals_per_s']:.3g} evals/s", file=sys.stderr, flush=True)
+        res[mode] = {key: v for key, v in r.items() if key != "results"}
+    return res
 
 
 def cpu_baseline(w, attr_h, imp_h, min_seconds):

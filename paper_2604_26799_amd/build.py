@@ -6,6 +6,8 @@ Every HIP source is compiled with:
   -fhip-fp32-correctly-rounded-divide-sqrt   IEEE division
   -fno-fast-math, denormals kept   (no -fgpu-flush-denormals-to-zero)
   -Xclang -target-feature -Xclang -packed-fp32-ops   no packed FP32 instructions
+  -mllvm -amdgpu-mfma-vgpr-form    MFMA results in ordinary VGPRs (the VQ epilogue
+                                   reads every score; no AGPR-to-VGPR copies)
 """
 from __future__ import annotations
 
@@ -28,7 +30,8 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include")]
 DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=off", "-fno-fast-math",
           "-fhip-fp32-correctly-rounded-divide-sqrt",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -26,6 +26,7 @@
 // option index in class order.
 #include <algorithm>
 #include <cmath>
+#include <climits>
 #include <cstdint>
 #include <cstring>
 #include <limits>
@@ -157,6 +158,29 @@ struct Completion {
             dlen.push_back(L); dcost.push_back(V); dslope.push_back(g.slope);
         }
     }
+    // Position cursors for evaluating h at monotonically decreasing D (states
+    // visited in increasing size): amortised O(1) instead of a binary search.
+    struct Cursor {
+        size_t ku = SIZE_MAX, kd = 0;
+    };
+    double h_at(int64_t D, Cursor& c) const {
+        if (D >= 0) {
+            // first k with ulen[k] >= D; D only decreases, so k only moves down
+            if (c.ku == SIZE_MAX) c.ku = ulen.size();
+            while (c.ku > 0 && ulen[c.ku - 1] >= D) --c.ku;
+            const size_t k = c.ku;
+            if (k == ulen.size()) return std::max(0.0, lambda * (double)D - (usave.empty() ? 0.0 : usave.back()));
+            double prevL = k ? (double)ulen[k - 1] : 0.0, prevV = k ? usave[k - 1] : 0.0;
+            return std::max(0.0, lambda * (double)D - prevV - (lambda - uslope[k]) * ((double)D - prevL));
+        }
+        // first k with dlen[k] >= F = -D; F only grows, so k only moves up
+        const int64_t F = -D;
+        while (c.kd < dlen.size() && dlen[c.kd] < F) ++c.kd;
+        const size_t k = c.kd;
+        if (k == dlen.size()) return kInf;
+        double prevL = k ? (double)dlen[k - 1] : 0.0, prevV = k ? dcost[k - 1] : 0.0;
+        return prevV + dslope[k] * ((double)F - prevL);
+    }
     double h(int64_t D) const {
         if (D >= 0) {
             size_t k = std::lower_bound(ulen.begin(), ulen.end(), D) - ulen.begin();
@@ -215,11 +239,13 @@ int core_dp(const std::vector<std::vector<Opt>>& opts, double e_fixed, int64_t c
         const double rest = e_fixed + mr[li + 1];
         comp.restrict_after((int64_t)li);
         // bound of a state after this layer: Lagrangian part + completion LP
-        auto bound = [&](int64_t w, double z) {
-            return rest + z - lambda * (double)(cap - w) + comp.h(cap - w - sr[li + 1]);
+        // (each caller visits states in increasing size through its own cursor)
+        auto bound = [&](int64_t w, double z, Completion::Cursor& cu) {
+            return rest + z - lambda * (double)(cap - w) + comp.h_at(cap - w - sr[li + 1], cu);
         };
         // k-way merge of cur + o[j] by (size, loss); heap of the list heads
         std::vector<int32_t> head(nopt_l, 0);
+        std::vector<Completion::Cursor> cursor(nopt_l);
         auto state_at = [&](int j, int32_t i) {
             return State{cur[i].w + o[j].s, cur[i].z + o[j].e, i, (int16_t)o[j].j};
         };
@@ -231,7 +257,7 @@ int core_dp(const std::vector<std::vector<Opt>>& opts, double e_fixed, int64_t c
         auto valid = [&](int j, int32_t i) {
             const State st = state_at(j, i);
             if (st.w > cap) return 0;  // the list is sorted by size: stop this list
-            if (bound(st.w, st.z) > UB + tol) return 1;  // skip
+            if (bound(st.w, st.z, cursor[j]) > UB + tol) return 1;  // skip
             return 2;
         };
         auto settle = [&](int j) {
@@ -286,7 +312,8 @@ int core_dp(const std::vector<std::vector<Opt>>& opts, double e_fixed, int64_t c
         if (beam && nxt.size() > beam) {
             // keep the `beam` states of least bound, in size order
             keys.resize(nxt.size());
-            for (size_t i = 0; i < nxt.size(); ++i) keys[i] = bound(nxt[i].w, nxt[i].z);
+            Completion::Cursor cu;
+            for (size_t i = 0; i < nxt.size(); ++i) keys[i] = bound(nxt[i].w, nxt[i].z, cu);
             std::vector<double> sel(keys);
             std::nth_element(sel.begin(), sel.begin() + (beam - 1), sel.end());
             const double cut = sel[beam - 1];

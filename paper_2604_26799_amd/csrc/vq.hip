@@ -19,12 +19,14 @@
 //      order).  The exact winner then satisfies s~_j <= min s~ + 2 E_i; a
 //      small FP64 slack 2 delta_i also admits the winner of the FP64
 //      definition when exact distances tie within FP64 rounding.
-//   3. Each lane keeps up to 12 candidates (s~ <= the row's running min +
-//      T_i, the minimum shared between the row's two lanes every tile);
-//      at the end the row's candidates under the final threshold are
+//   3. Two passes over the codebook.  Pass 1 keeps each lane's minimum
+//      score; the row minimum m (both lanes of the row) fixes the threshold
+//      m + T_i.  Pass 2 recomputes the scores and records, per lane, the
+//      tiles holding scores under the threshold with a mask of those
+//      codewords (up to 8 tiles per lane); the row's candidates are then
 //      re-scored with the FP64 definition (same operation order) and the
-//      smallest (distance, index) wins.  Rows whose buffer overflowed go to
-//      an exact FP64 full scan.
+//      smallest (distance, index) wins.  Rows with more candidate tiles than
+//      slots go to an exact FP64 full scan.
 // The result equals the FP64 definition bit for bit.
 #include <algorithm>
 #include <cmath>
@@ -40,10 +42,10 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int VQ_WAVES = 4;
 constexpr int VQ_THREADS = VQ_WAVES * MGS_WAVE;
-constexpr int VQ_ROWSETS = 2;                          // 32-row sets per wave
+constexpr int VQ_ROWSETS = 4;                          // 32-row sets per wave
 constexpr int VQ_ROWS = VQ_WAVES * VQ_ROWSETS * 32;    // rows per workgroup
 constexpr int VQ_CHUNK = 256;                          // codewords per LDS chunk
-constexpr int VQ_CAND = 12;                            // candidate slots per lane and row set
+constexpr int VQ_CAND = 8;                             // candidate slots per lane and row set (2^n; one stays free)
 
 struct VqArgs {
     const float* x;
@@ -105,8 +107,9 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
     constexpr int KP = 16 * KS;
     constexpr int LDS_STRIDE = KP + 8;  // bf16 elements; padding spreads LDS banks
     __shared__ __attribute__((aligned(16))) __bf16 cbs[VQ_CHUNK * LDS_STRIDE];
-    __shared__ float cand_s[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
-    __shared__ int32_t cand_j[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
+    // candidate tiles: tile index and the mask of the lane's codewords in it
+    __shared__ int32_t cand_t[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
+    __shared__ uint16_t cand_m[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -117,13 +120,11 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
     // ---- B operands (the X rows), bound T per row
     bf16x8 breg[VQ_ROWSETS][KS];
     float T[VQ_ROWSETS];
-    int64_t rows[VQ_ROWSETS];
     uint32_t bad = 0;
     const float cm = __uint_as_float(*a.cmax_bits);
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
         const int64_t r = row0 + rs * 32 + (lane & 31);
-        rows[rs] = r;
         float n2 = 0.0f;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -155,90 +156,96 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
     }
     if (bad) atomicOr(&a.status->nonfinite, 1u);
 
-    float mrow[VQ_ROWSETS];
+    float thr[VQ_ROWSETS];
     int cnt[VQ_ROWSETS];
-    int ovf[VQ_ROWSETS];
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-        mrow[rs] = INFINITY;
+        thr[rs] = INFINITY;
         cnt[rs] = 0;
-        ovf[rs] = 0;
     }
 
     const int units_per_row = KP / 8;  // 16-byte units
-    for (int c0 = 0; c0 < a.Kpad; c0 += VQ_CHUNK) {
-        const int nrows = min(VQ_CHUNK, a.Kpad - c0);
-        __syncthreads();
-        for (int uidx = tid; uidx < nrows * units_per_row; uidx += VQ_THREADS) {
-            const int r = uidx / units_per_row, part = uidx - r * units_per_row;
-            const uint4 v = *(const uint4*)(a.cbp + (int64_t)(c0 + r) * KP + part * 8);
-            *(uint4*)(cbs + r * LDS_STRIDE + part * 8) = v;
-        }
-        __syncthreads();
-        for (int tile = 0; tile < nrows / 32; ++tile) {
-            bf16x8 areg[KS];
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                areg[ks] = *(const bf16x8*)(cbs + (tile * 32 + (lane & 31)) * LDS_STRIDE + 16 * ks + 8 * half);
-            const int jbase = c0 + tile * 32;
-#pragma unroll
-            for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-                f32x16 acc = {};
+    // pass 0: minimum score per lane; pass 1: codewords under the threshold
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int c0 = 0; c0 < a.Kpad; c0 += VQ_CHUNK) {
+            const int nrows = min(VQ_CHUNK, a.Kpad - c0);
+            __syncthreads();
+            for (int uidx = tid; uidx < nrows * units_per_row; uidx += VQ_THREADS) {
+                const int r = uidx / units_per_row, part = uidx - r * units_per_row;
+                const uint4 v = *(const uint4*)(a.cbp + (int64_t)(c0 + r) * KP + part * 8);
+                *(uint4*)(cbs + r * LDS_STRIDE + part * 8) = v;
+            }
+            __syncthreads();
+            for (int tile = 0; tile < nrows / 32; ++tile) {
+                bf16x8 areg[KS];
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(areg[ks], breg[rs][ks], acc, 0, 0, 0);
-                float tmin = acc[0];
+                    areg[ks] =
+                        *(const bf16x8*)(cbs + (tile * 32 + (lane & 31)) * LDS_STRIDE + 16 * ks + 8 * half);
+                const int jbase = c0 + tile * 32;
+                // K steps outer, row sets inner: consecutive MFMAs are independent
+                // (each waits only on the one four issues earlier)
+                f32x16 acc[VQ_ROWSETS];
 #pragma unroll
-                for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[i]);
-                // running minimum of the whole row: the partner lane holds the
-                // other 16 codewords of this tile
-                mrow[rs] = fminf(mrow[rs], fminf(tmin, __shfl_xor(tmin, 32, MGS_WAVE)));
-                const float thr = mrow[rs] + T[rs];
-                if (tmin <= thr && !ovf[rs]) {
+                for (int rs = 0; rs < VQ_ROWSETS; ++rs) acc[rs] = f32x16{};
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const float s = acc[i];
-                        // output element i of this lane: codeword row 8*(i/4) + 4*half + i%4
-                        const int j = jbase + 8 * (i >> 2) + 4 * half + (i & 3);
-                        if (s <= thr && j < K && !ovf[rs]) {
-                            if (cnt[rs] == VQ_CAND) {
-                                int w = 0;
-                                for (int e = 0; e < VQ_CAND; ++e) {
-                                    float se = cand_s[wave][rs][e][lane];
-                                    if (se <= thr) {
-                                        cand_s[wave][rs][w][lane] = se;
-                                        cand_j[wave][rs][w][lane] = cand_j[wave][rs][e][lane];
-                                        ++w;
-                                    }
-                                }
-                                cnt[rs] = w;
-                                if (w == VQ_CAND) ovf[rs] = 1;
-                            }
-                            if (!ovf[rs]) {
-                                cand_s[wave][rs][cnt[rs]][lane] = s;
-                                cand_j[wave][rs][cnt[rs]][lane] = j;
-                                cnt[rs] += 1;
-                            }
-                        }
+                for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                    for (int rs = 0; rs < VQ_ROWSETS; ++rs)
+                        acc[rs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(areg[ks], breg[rs][ks], acc[rs], 0, 0, 0);
+#pragma unroll
+                for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
+                    float tmin = acc[rs][0];
+#pragma unroll
+                    for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
+                    if (pass == 0) {
+                        thr[rs] = fminf(thr[rs], tmin);  // pass 0 keeps the lane minimum here
+                    } else {
+                        // branch-free: every lane writes its mask of codewords under
+                        // the threshold into its next free slot, and the slot is
+                        // kept (the count advances) only when the mask is not empty
+                        uint32_t bits = 0;
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) bits |= (uint32_t)(acc[rs][i] <= thr[rs]) << i;
+                        const int slot = cnt[rs] & (VQ_CAND - 1);
+                        cand_t[wave][rs][slot][lane] = jbase;
+                        cand_m[wave][rs][slot][lane] = (uint16_t)bits;
+                        // VQ_CAND - 1 tiles are kept; a count of VQ_CAND marks the
+                        // overflow (the wrapped slot 0 is then never read: the row
+                        // takes the exact full scan)
+                        cnt[rs] += bits != 0u;
                     }
                 }
             }
+        }
+        if (pass == 0) {
+            // row minimum (the partner lane holds the other 16 codewords of
+            // every tile) plus the bound
+#pragma unroll
+            for (int rs = 0; rs < VQ_ROWSETS; ++rs)
+                thr[rs] = fminf(thr[rs], __shfl_xor(thr[rs], 32, MGS_WAVE)) + T[rs];
         }
     }
 
     // ---- exact FP64 re-rank of the row's candidates (both lanes of the row)
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-        const int64_t r = rows[rs];
-        const float thr = mrow[rs] + T[rs];
-        const int ovf_row = ovf[rs] | __shfl_xor(ovf[rs], 32, MGS_WAVE);
+        const int64_t r = row0 + rs * 32 + (lane & 31);
+        const int ovf = cnt[rs] >= VQ_CAND;
+        const int ovf_row = ovf | __shfl_xor(ovf, 32, MGS_WAVE);
         double best = INFINITY;
         int32_t bj = 0x7fffffff;
         if (r < a.N && !ovf_row) {
             const float* xr = a.x + r * D;
             for (int e = 0; e < cnt[rs]; ++e) {
-                if (cand_s[wave][rs][e][lane] <= thr) {
-                    const int32_t j = cand_j[wave][rs][e][lane];
+                const int jbase = cand_t[wave][rs][e][lane];
+                uint32_t bits = cand_m[wave][rs][e][lane];
+                while (bits) {
+                    const int i = __builtin_ctz(bits);
+                    bits &= bits - 1;
+                    // output element i of this lane: codeword row 8*(i/4) + 4*half + i%4
+                    const int32_t j = jbase + 8 * (i >> 2) + 4 * half + (i & 3);
+                    if (j >= K) continue;
                     const double d = exact_dist(xr, a.cb + (int64_t)j * D, D);
                     if (d < best || (d == best && j < bj)) {
                         best = d;

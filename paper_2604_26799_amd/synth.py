@@ -129,21 +129,32 @@ def workload(name: str) -> SweepWorkload:
 
 @dataclass
 class Job:
-    """One compression request of the serving stream."""
+    """One compression request of the serving stream: the first ``n`` Gaussians
+    of base scene ``base`` (``scene(BASE_N, 20, seed=1000 + base)``) and a byte
+    budget."""
     job_id: int
     arrival_s: float
     n: int
     budget_bytes: int
-    seed: int
+    base: int
     ratios: List[Fraction] = field(default_factory=list)
 
 
-def job_stream(num_jobs: int = 64, rate_per_s: float = 2.0, seed: int = 0,
-               n_lo: int = 200_000, n_hi: int = 6_000_000) -> List[Job]:
-    """Poisson arrivals; N log-uniform in [n_lo, n_hi]; budget ratio U(10, 60).
+BASE_N = 6_000_000   # Gaussians in each base scene of the serving stream
+NUM_BASES = 2
 
-    Each job's scene is ``scene(N, 20, seed=1000 + job_id)`` and it searches 16
-    reserve ratios uniformly spaced in [0.2, 0.95].
+
+def base_scene(base: int, n: int = BASE_N):
+    """Base scene ``base`` of the serving stream (its first ``n`` Gaussians)."""
+    return scene(n, 20, seed=1000 + base)
+
+
+def job_stream(num_jobs: int = 64, rate_per_s: float = 2.0, seed: int = 0,
+               n_lo: int = 200_000, n_hi: int = BASE_N, num_bases: int = NUM_BASES) -> List[Job]:
+    """Poisson arrivals; N log-uniform in [n_lo, n_hi]; budget ratio U(10, 60)
+    of the raw FP32 size (20 channels x 4 bytes per Gaussian).
+
+    Each job searches 16 reserve ratios uniformly spaced in [0.2, 0.95].
     """
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate_per_s, num_jobs)
@@ -154,5 +165,5 @@ def job_stream(num_jobs: int = 64, rate_per_s: float = 2.0, seed: int = 0,
     jobs = []
     for j in range(num_jobs):
         n = int(ns[j])
-        jobs.append(Job(j, float(arrivals[j]), n, int(n * 80 / ratio[j]), 1000 + j, list(ratios)))
+        jobs.append(Job(j, float(arrivals[j]), n, int(n * 80 / ratio[j]), j % num_bases, list(ratios)))
     return jobs
