@@ -311,13 +311,16 @@ def served_stream(num_jobs):
     store = serve.SceneStore()
     jobs = synth.job_stream(num_jobs, 2.0, seed=0)
     res = {"jobs": num_jobs, "arrivals_per_s": 2.0}
-    for mode in ("batched", "plain"):
-        srv = serve.Server(store, mode=mode)
-        r = srv.run(jobs)
-        srv.close()
-        print(f"served {mode}: p50 {r['p50_s']:.3f} s, p99 {r['p99_s']:.3f} s, "
-              f"{r['evals_per_s']:.3g} evals/s", file=sys.stderr, flush=True)
-        res[mode] = {key: v for key, v in r.items() if key != "results"}
+    # the stream as it arrives, then the same jobs all at once (saturation:
+    # the throughput each form sustains)
+    for label, scale in (("", 1.0), ("saturated_", 0.0)):
+        for mode in ("batched", "plain"):
+            srv = serve.Server(store, mode=mode)
+            r = srv.run(jobs, time_scale=scale)
+            srv.close()
+            print(f"served {label}{mode}: p50 {r['p50_s']:.3f} s, p99 {r['p99_s']:.3f} s, "
+                  f"{r['evals_per_s']:.3g} evals/s", file=sys.stderr, flush=True)
+            res[label + mode] = {key: v for key, v in r.items() if key != "results"}
     return res
 
 
