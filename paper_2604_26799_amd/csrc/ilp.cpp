@@ -42,7 +42,7 @@ namespace {
 
 constexpr double kInf = std::numeric_limits<double>::infinity();
 constexpr size_t kStateCap = 20u * 1000u * 1000u;
-constexpr size_t kBeam = 4000;  // states per layer in the incumbent passes
+constexpr size_t kBeam = 1000;  // states per layer in the incumbent passes
 
 struct Opt {
     double e;
@@ -527,7 +527,7 @@ struct Mckp {
     // cheapest in reduced cost improves the incumbent, which shrinks the gap;
     // once every class that can still change (rcmin <= gap) fits in the core,
     // one exact DP over exactly those classes finishes.
-    size_t K = 128;
+    size_t K = 32;
     for (;;) {
         const double gap = UB - LB0 + tol;
         std::vector<int64_t> need;
