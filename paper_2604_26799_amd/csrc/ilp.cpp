@@ -42,7 +42,10 @@ namespace {
 
 constexpr double kInf = std::numeric_limits<double>::infinity();
 constexpr size_t kStateCap = 20u * 1000u * 1000u;
-constexpr size_t kBeam = 1000;  // states per layer in the incumbent passes
+// Incumbent passes (beam width, first core size), tried in order: a cheap
+// schedule first; a wider one only when the exact pass of the cheaper one
+// exceeds the state limit (its weaker incumbent left too large a gap).
+constexpr struct { size_t beam, k0; } kSchedules[] = {{1000, 32}, {4000, 128}, {16000, 128}};
 
 struct Opt {
     double e;
@@ -508,7 +511,11 @@ struct Mckp {
         if (trivial) {
             for (int64_t c = 0; c < ncls; ++c) choice[c] = (uint8_t)cls[c].back().j;
         } else {
-            int rc = expand(choice);
+            int rc = MGS_ELIMIT;
+            for (const auto& sc : kSchedules) {
+                rc = expand(choice, sc.beam, sc.k0);
+                if (rc != MGS_ELIMIT) break;
+            }
             if (rc) return rc;
         }
         double o = 0.0;
@@ -522,12 +529,12 @@ struct Mckp {
         return MGS_OK;
     }
 
-    int expand(uint8_t* choice) {
+    int expand(uint8_t* choice, size_t beam, size_t k0) {
     // ---- 4. expanding core: DP over the classes whose alternatives are
     // cheapest in reduced cost improves the incumbent, which shrinks the gap;
     // once every class that can still change (rcmin <= gap) fits in the core,
     // one exact DP over exactly those classes finishes.
-    size_t K = 32;
+    size_t K = k0;
     for (;;) {
         const double gap = UB - LB0 + tol;
         std::vector<int64_t> need;
@@ -554,7 +561,7 @@ struct Mckp {
         std::vector<int16_t> pick;
         double zb = 0.0;
         int rc = core_dp(opts, e_fixed, budget - s_fixed, lambda, UB, tol,
-                         final_pass ? 0 : kBeam, pick);
+                         final_pass ? 0 : beam, pick);
         if (rc == MGS_ELIMIT) return rc;
         if (final_pass) {
             if (rc != MGS_OK) return MGS_EINFEASIBLE;  // (cannot happen: the incumbent is a state)

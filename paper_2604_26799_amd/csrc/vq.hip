@@ -44,7 +44,7 @@ constexpr int VQ_WAVES = 4;
 constexpr int VQ_THREADS = VQ_WAVES * MGS_WAVE;
 constexpr int VQ_ROWSETS = 4;                          // 32-row sets per wave
 constexpr int VQ_ROWS = VQ_WAVES * VQ_ROWSETS * 32;    // rows per workgroup
-constexpr int VQ_CHUNK = 256;                          // codewords per LDS chunk
+constexpr int VQ_CHUNK = 128;                          // codewords per LDS chunk (two buffers)
 constexpr int VQ_CAND = 8;                             // candidate slots per lane and row set (2^n; one stays free)
 
 struct VqArgs {
@@ -105,8 +105,10 @@ __device__ __forceinline__ double exact_dist(const float* __restrict__ x, const 
 template <int KS>
 __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
     constexpr int KP = 16 * KS;
-    constexpr int LDS_STRIDE = KP + 8;  // bf16 elements; padding spreads LDS banks
-    __shared__ __attribute__((aligned(16))) __bf16 cbs[VQ_CHUNK * LDS_STRIDE];
+    constexpr int UNITS = KP / 8;  // 16-byte units per prepared codeword
+    // two chunk buffers, filled by direct global-to-LDS loads (64 lanes x 16
+    // contiguous bytes per instruction, so the rows are not padded)
+    __shared__ __attribute__((aligned(16))) __bf16 cbs[2][VQ_CHUNK * KP];
     // candidate tiles: tile index and the mask of the lane's codewords in it
     __shared__ int32_t cand_t[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
     __shared__ uint16_t cand_m[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
@@ -164,24 +166,43 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
         cnt[rs] = 0;
     }
 
-    const int units_per_row = KP / 8;  // 16-byte units
+    // Asynchronous copy of chunk c0 of the prepared codebook into buffer
+    // `buf`: wave w moves units [(i*VQ_WAVES + w)*64, +64) of the chunk; the
+    // LDS base of each instruction is uniform over the wave.
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    auto prefetch = [&](int c0, int buf) {
+        const int nunits = min(VQ_CHUNK, a.Kpad - c0) * UNITS;
+        const char* src = (const char*)(a.cbp + (int64_t)c0 * KP);
+#pragma unroll
+        for (int i = 0; i < (VQ_CHUNK * UNITS + VQ_THREADS - 1) / VQ_THREADS; ++i) {
+            const int ublk = (i * VQ_WAVES + wave_u) * MGS_WAVE;
+            if (ublk + lane < nunits)
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(src + (size_t)(ublk + lane) * 16),
+                    (__attribute__((address_space(3))) void*)((char*)&cbs[buf][0] + ublk * 16), 16, 0, 0);
+        }
+    };
+    const int nchunks = (a.Kpad + VQ_CHUNK - 1) / VQ_CHUNK;
+    prefetch(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     // pass 0: minimum score per lane; pass 1: codewords under the threshold
     for (int pass = 0; pass < 2; ++pass) {
-        for (int c0 = 0; c0 < a.Kpad; c0 += VQ_CHUNK) {
+        for (int ci = 0; ci < nchunks; ++ci) {
+            const int buf = (pass * nchunks + ci) & 1;
+            const int c0 = ci * VQ_CHUNK;
             const int nrows = min(VQ_CHUNK, a.Kpad - c0);
-            __syncthreads();
-            for (int uidx = tid; uidx < nrows * units_per_row; uidx += VQ_THREADS) {
-                const int r = uidx / units_per_row, part = uidx - r * units_per_row;
-                const uint4 v = *(const uint4*)(a.cbp + (int64_t)(c0 + r) * KP + part * 8);
-                *(uint4*)(cbs + r * LDS_STRIDE + part * 8) = v;
-            }
-            __syncthreads();
+            // the other buffer was last read before the barrier that ended
+            // the previous chunk: fill it with the next chunk (pass 1 restarts
+            // at chunk 0) while this one is processed
+            if (ci + 1 < nchunks) prefetch(c0 + VQ_CHUNK, buf ^ 1);
+            else if (pass == 0) prefetch(0, buf ^ 1);
+            const __bf16* cb_l = &cbs[buf][0];
             for (int tile = 0; tile < nrows / 32; ++tile) {
                 bf16x8 areg[KS];
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
-                    areg[ks] =
-                        *(const bf16x8*)(cbs + (tile * 32 + (lane & 31)) * LDS_STRIDE + 16 * ks + 8 * half);
+                    areg[ks] = *(const bf16x8*)(cb_l + (tile * 32 + (lane & 31)) * KP + 16 * ks + 8 * half);
                 const int jbase = c0 + tile * 32;
                 // K steps outer, row sets inner: consecutive MFMAs are independent
                 // (each waits only on the one four issues earlier)
@@ -204,9 +225,14 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
                         // branch-free: every lane writes its mask of codewords under
                         // the threshold into its next free slot, and the slot is
                         // kept (the count advances) only when the mask is not empty
-                        uint32_t bits = 0;
+                        // sign bits of thr - s, shifted in by v_alignbit (element i
+                        // lands in bit 15 - i); s <= thr  <=>  thr - s >= 0 (an exact
+                        // zero difference is +0), so the mask is the complement
+                        uint32_t neg = 0;
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) bits |= (uint32_t)(acc[rs][i] <= thr[rs]) << i;
+                        for (int i = 0; i < 16; ++i)
+                            neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(thr[rs] - acc[rs][i]), 31);
+                        const uint32_t bits = ~neg & 0xFFFFu;
                         const int slot = cnt[rs] & (VQ_CAND - 1);
                         cand_t[wave][rs][slot][lane] = jbase;
                         cand_m[wave][rs][slot][lane] = (uint16_t)bits;
@@ -217,6 +243,8 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
                     }
                 }
             }
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next chunk has landed
+            __syncthreads();                // ... and everyone's; this buffer is free
         }
         if (pass == 0) {
             // row minimum (the partner lane holds the other 16 codewords of
@@ -241,7 +269,7 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
                 const int jbase = cand_t[wave][rs][e][lane];
                 uint32_t bits = cand_m[wave][rs][e][lane];
                 while (bits) {
-                    const int i = __builtin_ctz(bits);
+                    const int i = 15 - __builtin_ctz(bits);  // bit 15 - i holds element i
                     bits &= bits - 1;
                     // output element i of this lane: codeword row 8*(i/4) + 4*half + i%4
                     const int32_t j = jbase + 8 * (i >> 2) + 4 * half + (i & 3);

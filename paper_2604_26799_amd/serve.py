@@ -242,9 +242,16 @@ class Server:
         return st
 
     def _solve(self, live: _Live):
+        """The job's search; a library error (e.g. the exact ILP's state limit)
+        fails this job only, with the code in its result."""
         job = live.job
-        return mgs.search(job.n, CHANNELS, live.k, self.G, self.bits, live.host["err"].numpy(),
-                          live.host["bits"].numpy(), 8 * job.budget_bytes, threads=self.ilp_threads)
+        try:
+            res = mgs.search(job.n, CHANNELS, live.k, self.G, self.bits, live.host["err"].numpy(),
+                             live.host["bits"].numpy(), 8 * job.budget_bytes, threads=self.ilp_threads)
+            res["code"] = mgs.OK
+        except mgs.MgsError as e:
+            res = {"best_t": -1, "best_bits": None, "code": e.code}
+        return res
 
     def _launch_codes(self, live: _Live):
         torch = self.torch
@@ -339,7 +346,8 @@ class Server:
                 results.append(JobResult(job.job_id, job.n, job.arrival_s * time_scale, live.t_admit,
                                          live.t_swept, live.t_solved, now(),
                                          int(live.k.sum()) * CHANNELS * nb, res["best_t"],
-                                         None if res["best_bits"] is None else res["best_bits"].copy(), codes))
+                                         None if res["best_bits"] is None else res["best_bits"].copy(), codes,
+                                         res["code"]))
                 live.dev.clear()
                 live.host.clear()
                 self.adm.release(live.need)
@@ -355,7 +363,8 @@ class Server:
         return {"results": results,
                 "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                 "mean_s": float(lat.mean()), "evals_per_s": evals / (last - first), "wall_s": last - first,
-                "jobs": len(results), "launches": self.launches,
+                "jobs": len(results), "failed": sum(1 for r in results if r.status != mgs.OK),
+                "launches": self.launches,
                 "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
                 "max_batch": int(max(self.batch_sizes)) if self.batch_sizes else 0}
 
