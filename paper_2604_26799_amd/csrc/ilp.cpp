@@ -353,12 +353,29 @@ struct Mckp {
     int64_t ncls;
     int nopt;
     int64_t budget;
-    std::vector<std::vector<Opt>> cls;
+    // the options of every class without dominated ones, sorted by size,
+    // in one array: class c is opt[coff[c] .. coff[c+1])
+    std::vector<Opt> opt;
+    std::vector<int64_t> coff;
+    struct Span {
+        const Opt* p;
+        int n;
+        const Opt& operator[](int i) const { return p[i]; }
+        int size() const { return n; }
+        const Opt& front() const { return p[0]; }
+        const Opt& back() const { return p[n - 1]; }
+        const Opt* begin() const { return p; }
+        const Opt* end() const { return p + n; }
+    };
+    Span cls(int64_t c) const { return Span{opt.data() + coff[c], (int)(coff[c + 1] - coff[c])}; }
     std::vector<int> inc_pos, lagbest;
     std::vector<double> mlam, rcmin;
     std::vector<int64_t> order;
     double lambda = 0.0, LB0 = 0.0, UB = 0.0, tol = 0.0;
     bool trivial = false;  // the unconstrained optimum fits the budget
+    std::vector<int> greedy_pos;  // LP greedy solution (its integral part)
+    int64_t greedy_cap = 0;       // capacity it leaves
+    bool solve_ready = false;     // phase 2 done
 
     Mckp(const double* e, const int64_t* s, int64_t n, int o, int64_t b)
         : err(e), size(s), ncls(n), nopt(o), budget(b) {}
@@ -366,94 +383,159 @@ struct Mckp {
     // Lower bound on the optimum (the optimum itself when trivial).
     double lower_bound() const { return LB0; }
 
+    // Both phases (the single-instance solver).
     int prepare() {
+        int rc = prepare_bound();
+        if (rc == MGS_OK && !trivial) prepare_solve();
+        return rc;
+    }
+
+    // Phase 1, enough for the lower bound: options without dominated ones,
+    // the LP relaxation (lambda) and the Lagrangian bound.
+    int prepare_bound() {
     // ---- 1. per-class options without dominated ones, sorted by size
-    cls.assign(ncls, {});
-    int64_t min_total = 0;
+    opt.clear();
+    opt.reserve((size_t)ncls * nopt);
+    coff.assign(ncls + 1, 0);
+    int64_t min_total = 0, max_total = 0;
+    double max_obj = 0.0;
+    Opt o[256];
     for (int64_t c = 0; c < ncls; ++c) {
-        std::vector<Opt> o;
-        o.reserve(nopt);
-        for (int j = 0; j < nopt; ++j) o.push_back({err[c * nopt + j], size[c * nopt + j], j});
-        std::sort(o.begin(), o.end(), [](const Opt& a, const Opt& b) {
-            if (a.s != b.s) return a.s < b.s;
-            if (a.e != b.e) return a.e < b.e;
-            return a.j < b.j;
-        });
-        std::vector<Opt> keep;
-        for (const Opt& x : o)
-            if (keep.empty() || x.e < keep.back().e) keep.push_back(x);
-        min_total += keep.front().s;
-        cls[c] = std::move(keep);
+        for (int j = 0; j < nopt; ++j) o[j] = {err[c * nopt + j], size[c * nopt + j], j};
+        // insertion sort by (size, loss, index): the options of a class are
+        // few and nearly sorted already (sizes grow with the bit-width)
+        for (int i = 1; i < nopt; ++i) {
+            const Opt x = o[i];
+            int k = i;
+            while (k > 0 && (o[k - 1].s > x.s || (o[k - 1].s == x.s && (o[k - 1].e > x.e ||
+                                                                         (o[k - 1].e == x.e && o[k - 1].j > x.j))))) {
+                o[k] = o[k - 1];
+                --k;
+            }
+            o[k] = x;
+        }
+        const size_t first = opt.size();
+        for (int i = 0; i < nopt; ++i)
+            if (opt.size() == first || o[i].e < opt.back().e) opt.push_back(o[i]);
+        coff[c + 1] = (int64_t)opt.size();
+        min_total += opt[first].s;
+        max_total += opt.back().s;
+        max_obj += opt.back().e;
     }
     if (min_total > budget) return MGS_EINFEASIBLE;
     // unconstrained optimum (last option of each class) fits: done
-    {
-        int64_t tot = 0;
-        for (auto& k : cls) tot += k.back().s;
-        if (tot <= budget) {
-            trivial = true;
-            double o = 0;
-            for (int64_t c = 0; c < ncls; ++c) o += cls[c].back().e;
-            LB0 = UB = o;
-            return MGS_OK;
-        }
+    if (max_total <= budget) {
+        trivial = true;
+        LB0 = UB = max_obj;
+        return MGS_OK;
     }
 
-    // ---- 2. LP relaxation via hull increments
-    struct Inc {
-        double eff;  // loss decrease per unit of size
-        int64_t c;
-        int from, to;  // positions in cls[c]
-    };
-    std::vector<Inc> incs;
+    // ---- 2. LP relaxation: greedy over the lower-hull increments of all
+    // classes by decreasing efficiency (loss saved per bit), ties by class and
+    // hull position, until one does not fit; its efficiency is lambda.  Each
+    // class's increments are already in decreasing efficiency (convex hull),
+    // so a heap merge of the classes yields that order and stops at the split.
+    std::vector<int> hv;                    // hull vertices (option positions), all classes
+    std::vector<int64_t> hoff(ncls + 1, 0);  // class c: hv[hoff[c] .. hoff[c+1])
+    hv.reserve((size_t)ncls * 4);
     for (int64_t c = 0; c < ncls; ++c) {
-        const auto& o = cls[c];
-        std::vector<int> hull{0};
+        const auto& o = cls(c);
+        const size_t h0 = hv.size();
+        hv.push_back(0);
         for (int i = 1; i < (int)o.size(); ++i) {
-            while (hull.size() >= 2) {
-                const Opt& a = o[hull[hull.size() - 2]];
-                const Opt& b = o[hull.back()];
+            while (hv.size() - h0 >= 2) {
+                const Opt& a = o[hv[hv.size() - 2]];
+                const Opt& b = o[hv.back()];
                 // drop b if it lies on or above the segment a -> o[i]
                 double lhs = (b.e - a.e) * (double)(o[i].s - a.s);
                 double rhs = (o[i].e - a.e) * (double)(b.s - a.s);
-                if (lhs >= rhs) hull.pop_back();
+                if (lhs >= rhs) hv.pop_back();
                 else break;
             }
-            hull.push_back(i);
+            hv.push_back(i);
         }
-        for (size_t h = 1; h < hull.size(); ++h) {
-            const Opt& a = o[hull[h - 1]];
-            const Opt& b = o[hull[h]];
-            incs.push_back({(a.e - b.e) / (double)(b.s - a.s), c, hull[h - 1], hull[h]});
-        }
+        hoff[c + 1] = (int64_t)hv.size();
     }
-    std::stable_sort(incs.begin(), incs.end(), [](const Inc& a, const Inc& b) { return a.eff > b.eff; });
+    struct Head {
+        double eff;
+        int64_t c;
+        int64_t h;  // index in hv of the increment's end vertex
+    };
+    auto eff_of = [&](int64_t c, int64_t h) {
+        const Opt& a = cls(c)[hv[h - 1]];
+        const Opt& b = cls(c)[hv[h]];
+        return (a.e - b.e) / (double)(b.s - a.s);
+    };
+    // max-heap on (eff, then smaller class first)
+    auto later = [](const Head& x, const Head& y) {
+        if (x.eff != y.eff) return x.eff < y.eff;
+        return x.c > y.c;
+    };
+    std::vector<Head> heap;
+    heap.reserve((size_t)ncls);
+    for (int64_t c = 0; c < ncls; ++c)
+        if (hoff[c + 1] - hoff[c] >= 2) heap.push_back({eff_of(c, hoff[c] + 1), c, hoff[c] + 1});
+    std::make_heap(heap.begin(), heap.end(), later);
     std::vector<int> pos(ncls, 0);  // current option position per class
     int64_t cap = budget - min_total;
     lambda = 0.0;
-    bool split = false;
-    for (const Inc& in : incs) {
-        if (pos[in.c] != in.from) continue;  // (cannot happen for a convex hull)
-        int64_t ds = cls[in.c][in.to].s - cls[in.c][in.from].s;
-        if (ds <= cap) {
-            cap -= ds;
-            pos[in.c] = in.to;
-        } else {
-            lambda = in.eff;
-            split = true;
+    while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end(), later);
+        const Head hd = heap.back();
+        heap.pop_back();
+        const int from = hv[hd.h - 1], to = hv[hd.h];
+        const int64_t ds = cls(hd.c)[to].s - cls(hd.c)[from].s;
+        if (ds > cap) {
+            lambda = hd.eff;
             break;
         }
+        cap -= ds;
+        pos[hd.c] = to;
+        if (hd.h + 1 < hoff[hd.c + 1]) {
+            heap.push_back({eff_of(hd.c, hd.h + 1), hd.c, hd.h + 1});
+            std::push_heap(heap.begin(), heap.end(), later);
+        }
     }
-    if (!split) lambda = 0.0;
+    greedy_pos = std::move(pos);
+    greedy_cap = cap;
+
+    // ---- 3. Lagrangian bound, reduced costs, Lagrangian-best option per class
+    mlam.assign(ncls, 0.0);
+    lagbest.assign(ncls, 0);
+    LB0 = -lambda * (double)budget;
+    double scale = 0.0;
+    for (int64_t c = 0; c < ncls; ++c) {
+        double m = kInf;
+        for (int i = 0; i < (int)cls(c).size(); ++i) {
+            double v = cls(c)[i].e + lambda * (double)cls(c)[i].s;
+            if (v < m) {  // options are sorted by size: ties keep the smaller size
+                m = v;
+                lagbest[c] = i;
+            }
+        }
+        mlam[c] = m;
+        LB0 += m;
+        scale = std::max(scale, std::fabs(m));
+    }
+    // slack for the rounding of bounds (UB is close to LB0, so it adds nothing)
+    tol = 1e-9 * (scale + std::fabs(LB0) + std::fabs(lambda * (double)budget)) + 1e-300;
+    return MGS_OK;
+    }
+
+    // Phase 2, before an exact solve: the incumbent, the reduced costs and
+    // the order of the classes by their cheapest alternative.
+    void prepare_solve() {
+    if (solve_ready || trivial) return;
+    int64_t cap = greedy_cap;
     // incumbent: greedy solution improved by single-class moves
-    inc_pos = pos;
+    inc_pos = greedy_pos;
     {
         bool improved = true;
         int rounds = 0;
         while (improved && rounds++ < 8) {
             improved = false;
             for (int64_t c = 0; c < ncls; ++c) {
-                const auto& o = cls[c];
+                const auto& o = cls(c);
                 int best = inc_pos[c];
                 double gain = 0.0;
                 for (int i = 0; i < (int)o.size(); ++i) {
@@ -473,43 +555,26 @@ struct Mckp {
         }
     }
     UB = 0.0;
-    for (int64_t c = 0; c < ncls; ++c) UB += cls[c][inc_pos[c]].e;
-
-    // ---- 3. Lagrangian bound, reduced costs, Lagrangian-best option per class
-    mlam.assign(ncls, 0.0);
-    lagbest.assign(ncls, 0);
-    LB0 = -lambda * (double)budget;
-    double scale = std::fabs(UB);
-    for (int64_t c = 0; c < ncls; ++c) {
-        double m = kInf;
-        for (int i = 0; i < (int)cls[c].size(); ++i) {
-            double v = cls[c][i].e + lambda * (double)cls[c][i].s;
-            if (v < m) {  // options are sorted by size: ties keep the smaller size
-                m = v;
-                lagbest[c] = i;
-            }
-        }
-        mlam[c] = m;
-        LB0 += m;
-        scale = std::max(scale, std::fabs(m));
-    }
-    tol = 1e-9 * (scale + std::fabs(LB0) + std::fabs(lambda * (double)budget)) + 1e-300;
+    for (int64_t c = 0; c < ncls; ++c) UB += cls(c)[inc_pos[c]].e;
     // smallest reduced cost of any other option of the class
     rcmin.assign(ncls, kInf);
     for (int64_t c = 0; c < ncls; ++c)
-        for (int i = 0; i < (int)cls[c].size(); ++i)
+        for (int i = 0; i < (int)cls(c).size(); ++i)
             if (i != lagbest[c])
-                rcmin[c] = std::min(rcmin[c], cls[c][i].e + lambda * (double)cls[c][i].s - mlam[c]);
+                rcmin[c] = std::min(rcmin[c], cls(c)[i].e + lambda * (double)cls(c)[i].s - mlam[c]);
     order.resize(ncls);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int64_t a, int64_t b) { return rcmin[a] < rcmin[b]; });
-    return MGS_OK;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        if (rcmin[a] != rcmin[b]) return rcmin[a] < rcmin[b];
+        return a < b;
+    });
+    solve_ready = true;
     }
 
     int exact(uint8_t* choice, double* obj, int64_t* used) {
+        prepare_solve();  // (no-op when done already or trivial)
         if (trivial) {
-            for (int64_t c = 0; c < ncls; ++c) choice[c] = (uint8_t)cls[c].back().j;
+            for (int64_t c = 0; c < ncls; ++c) choice[c] = (uint8_t)cls(c).back().j;
         } else {
             int rc = MGS_ELIMIT;
             for (const auto& sc : kSchedules) {
@@ -551,12 +616,12 @@ struct Mckp {
         int64_t s_fixed = 0;
         for (int64_t c = 0; c < ncls; ++c)
             if (!in_core[c]) {
-                e_fixed += cls[c][lagbest[c]].e;
-                s_fixed += cls[c][lagbest[c]].s;
+                e_fixed += cls(c)[lagbest[c]].e;
+                s_fixed += cls(c)[lagbest[c]].s;
             }
         std::vector<std::vector<Opt>> opts(core.size());
         for (size_t i = 0; i < core.size(); ++i)
-            for (const Opt& x : cls[core[i]])
+            for (const Opt& x : cls(core[i]))
                 if (x.e + lambda * (double)x.s - mlam[core[i]] <= gap) opts[i].push_back(x);
         std::vector<int16_t> pick;
         double zb = 0.0;
@@ -566,7 +631,7 @@ struct Mckp {
         if (final_pass) {
             if (rc != MGS_OK) return MGS_EINFEASIBLE;  // (cannot happen: the incumbent is a state)
             for (int64_t c = 0; c < ncls; ++c)
-                if (!in_core[c]) choice[c] = (uint8_t)cls[c][lagbest[c]].j;
+                if (!in_core[c]) choice[c] = (uint8_t)cls(c)[lagbest[c]].j;
             for (size_t i = 0; i < core.size(); ++i) choice[core[i]] = (uint8_t)pick[i];
             break;
         }
@@ -688,7 +753,7 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
             continue;
         }
         inst[t].reset(new Mckp(E[t].data(), S[t].data(), ncls, nb, budget_bits));
-        rc = inst[t]->prepare();
+        rc = inst[t]->prepare_bound();  // the rest only for the ratios that are solved
         if (rc == MGS_EINFEASIBLE) state[t] = MGS_SEARCH_INFEASIBLE;
         else st[t] = rc;
     }
