@@ -45,7 +45,7 @@ constexpr int VQ_THREADS = VQ_WAVES * MGS_WAVE;
 constexpr int VQ_ROWSETS = 4;                          // 32-row sets per wave
 constexpr int VQ_ROWS = VQ_WAVES * VQ_ROWSETS * 32;    // rows per workgroup
 constexpr int VQ_CHUNK = 128;                          // codewords per LDS chunk (two buffers)
-constexpr int VQ_CAND = 8;                             // candidate slots per lane and row set (2^n; one stays free)
+constexpr int VQ_CAND = 8;                             // candidate tiles per lane and row set
 
 struct VqArgs {
     const float* x;
@@ -198,15 +198,13 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
             if (ci + 1 < nchunks) prefetch(c0 + VQ_CHUNK, buf ^ 1);
             else if (pass == 0) prefetch(0, buf ^ 1);
             const __bf16* cb_l = &cbs[buf][0];
-            for (int tile = 0; tile < nrows / 32; ++tile) {
+            // scores of one 32-codeword tile for the wave's row sets; K steps
+            // outer, row sets inner: consecutive MFMAs are independent
+            auto scores = [&](int tile, f32x16 (&acc)[VQ_ROWSETS]) {
                 bf16x8 areg[KS];
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
                     areg[ks] = *(const bf16x8*)(cb_l + (tile * 32 + (lane & 31)) * KP + 16 * ks + 8 * half);
-                const int jbase = c0 + tile * 32;
-                // K steps outer, row sets inner: consecutive MFMAs are independent
-                // (each waits only on the one four issues earlier)
-                f32x16 acc[VQ_ROWSETS];
 #pragma unroll
                 for (int rs = 0; rs < VQ_ROWSETS; ++rs) acc[rs] = f32x16{};
 #pragma unroll
@@ -214,17 +212,21 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
 #pragma unroll
                     for (int rs = 0; rs < VQ_ROWSETS; ++rs)
                         acc[rs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(areg[ks], breg[rs][ks], acc[rs], 0, 0, 0);
+            };
+            auto epilogue = [&](int tile, const f32x16 (&acc)[VQ_ROWSETS]) {
+                const int jbase = c0 + tile * 32;
 #pragma unroll
                 for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-                    float tmin = acc[rs][0];
-#pragma unroll
-                    for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
                     if (pass == 0) {
+                        float tmin = acc[rs][0];
+#pragma unroll
+                        for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
                         thr[rs] = fminf(thr[rs], tmin);  // pass 0 keeps the lane minimum here
                     } else {
-                        // branch-free: every lane writes its mask of codewords under
-                        // the threshold into its next free slot, and the slot is
-                        // kept (the count advances) only when the mask is not empty
+                        float tmin = acc[rs][0];
+#pragma unroll
+                        for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
+                        if (tmin > thr[rs]) continue;  // most lane-tiles hold no candidate
                         // sign bits of thr - s, shifted in by v_alignbit (element i
                         // lands in bit 15 - i); s <= thr  <=>  thr - s >= 0 (an exact
                         // zero difference is +0), so the mask is the complement
@@ -233,15 +235,33 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
                         for (int i = 0; i < 16; ++i)
                             neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(thr[rs] - acc[rs][i]), 31);
                         const uint32_t bits = ~neg & 0xFFFFu;
-                        const int slot = cnt[rs] & (VQ_CAND - 1);
-                        cand_t[wave][rs][slot][lane] = jbase;
-                        cand_m[wave][rs][slot][lane] = (uint16_t)bits;
-                        // VQ_CAND - 1 tiles are kept; a count of VQ_CAND marks the
-                        // overflow (the wrapped slot 0 is then never read: the row
-                        // takes the exact full scan)
-                        cnt[rs] += bits != 0u;
+                        if (cnt[rs] < VQ_CAND) {
+                            cand_t[wave][rs][cnt[rs]][lane] = jbase;
+                            cand_m[wave][rs][cnt[rs]][lane] = (uint16_t)bits;
+                        }
+                        cnt[rs] += 1;  // a count past VQ_CAND marks the overflow
                     }
                 }
+            };
+            // software pipeline: the next tile's MFMAs are issued before this
+            // tile's epilogue, so the matrix cores work while the VALU does
+            // (two accumulator sets, alternating)
+            const int ntiles = nrows / 32;
+            f32x16 acc0[VQ_ROWSETS], acc1[VQ_ROWSETS];
+            scores(0, acc0);
+            int tile = 0;
+            for (; tile + 2 < ntiles; tile += 2) {
+                scores(tile + 1, acc1);
+                epilogue(tile, acc0);
+                scores(tile + 2, acc0);
+                epilogue(tile + 1, acc1);
+            }
+            if (tile + 1 < ntiles) {
+                scores(tile + 1, acc1);
+                epilogue(tile, acc0);
+                epilogue(tile + 1, acc1);
+            } else {
+                epilogue(tile, acc0);
             }
             __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next chunk has landed
             __syncthreads();                // ... and everyone's; this buffer is free
@@ -259,7 +279,7 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
         const int64_t r = row0 + rs * 32 + (lane & 31);
-        const int ovf = cnt[rs] >= VQ_CAND;
+        const int ovf = cnt[rs] > VQ_CAND;
         const int ovf_row = ovf | __shfl_xor(ovf, 32, MGS_WAVE);
         double best = INFINITY;
         int32_t bj = 0x7fffffff;
