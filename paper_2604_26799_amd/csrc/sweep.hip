@@ -37,19 +37,24 @@
 //      operands are exact.
 // Loss.  On those fast groups the values and steps are scaled by 2^-E with
 // 2^E <= R < 2^(E+1); both scalings are exact, so the FP32 dequantized value
-// is exactly xhat * 2^-E and every difference stays far from FP32 overflow
-// and underflow.  Each thread forms d = fl(xhat' - x'), and sums w * d^2
-// over its <= EPT elements in FP32 (relative error <= (EPT + 3) * 2^-24);
-// the partials are rescaled by 2^(2E) and reduced in FP64 in a fixed order,
-// so results are deterministic.  Literal-division groups and underflowed
-// steps keep exact FP64 terms.
+// is exactly xhat * 2^-E and every difference stays far from FP32 overflow.
+// Each thread forms d = fl(xhat' - x'), and sums w * d^2 over its <= EPT
+// elements in FP32; a fixed-order FP32 reduction over the wavefront follows
+// (relative error <= (EPT + 9) * 2^-24 for these nonnegative terms), then
+// the rescaling by 2^(2E) and an FP64 sum over waves, so results are
+// deterministic.  A wave total that is not finite, or so small that
+// underflowed terms could matter (below (W + 1) * 2^-112, W the largest
+// weight of the group), is recomputed from the registers with FP64 terms.
+// Literal-division groups and underflowed steps keep exact FP64 terms.
 // Size.  n log2 n - sum_k h_k log2 h_k in FP64.  Scanned histograms take
 // h log2 h per bin (LDS table for h < 256).  Histograms with more bins than
 // half the group instead add, per element, the increment of its bin's old
 // count c (returned by the atomic): F[c] = R(T(c+1)) - R(T(c)) with
 // T(h) = h log2 h and R the rounding to a 2^-K grid, so a bin's increments
 // telescope to R(T(h)) exactly and in any order.  The LDS copy of F covers
-// c < 255; rarer larger counts are settled by a correction scan.
+// c < 256 and is indexed by c mod 256; a bin that ends with h > 256 has
+// then collected floor(h / 256) * R(T(256)) + R(T(h mod 256)), which a
+// correction scan replaces by R(T(h)) (exact: all terms lie on the grid).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -93,63 +98,80 @@ struct Part {
     double ent;
 };
 
-// Entropy increment of one more element in a bin that held c before: the
-// LDS table covers c < LGTAB - 1; its last entry is 0 and flags the rare
-// bins that grow past it, which the correction scan settles afterwards.
-__device__ __forceinline__ void add_increment(uint32_t c, const double* lf, Part& acc,
-                                              uint32_t& ovf) {
-    acc.ent += lf[c < (uint32_t)(LGTAB - 1) ? c : (uint32_t)(LGTAB - 1)];
-    ovf |= (uint32_t)(c >= (uint32_t)(LGTAB - 1));
+// Entropy increment of one more element in a bin whose counter read c
+// before (the low 8 bits index the LDS table; the caller tracks larger
+// counts for the correction scan).
+__device__ __forceinline__ void add_increment(uint32_t c, const double* lf, Part& acc) {
+    acc.ent += lf[c & (uint32_t)(LGTAB - 1)];
+}
+
+// Counter bits that reveal a count of 256 or more: every 16-bit half of a
+// packed word, or the whole word.
+__device__ __forceinline__ uint32_t big_count_mask(bool packed) {
+    return packed ? 0xFF00FF00u : 0xFFFFFF00u;
 }
 
 // One histogram pass over the tile's elements for one bit-width on the fast
 // path (x / S_b from x / R, 2^23 rounding trick), specialised on packed bins,
-// ragged group and incremental entropy (RTN: the atomic's old count c gives
-// the entropy increment F[c]; no scan of the bins afterwards).
+// ragged group, incremental entropy (RTN: the atomic's old count c gives
+// the entropy increment F[c]; no scan of the bins afterwards), replicated
+// bins, a bin window and whether the pass also sums the loss.
 // xv holds x * 2^-E and Ss = S * 2^-E: both scalings are exact, so the
 // dequantized value (q - Z) * Ss is exactly xhat * 2^-E.
 // REPL: 2^rl copies of every bin, bin q of lane l in word (q << rl) | cpy with
 // cpy = l mod 2^rl, so lanes that share a bin hit different LDS banks.
-template <int NT, int EPT, bool PACKED, bool CHECK, bool RTN, bool REPL>
+// WIN: only words [lo, lo + nwords) live in LDS this pass; elements past the
+// ragged end carry w = 0 and x = 0, so they add nothing to the loss.
+// Returns the OR of the counters the pass read (RTN) in `seen`.
+template <int NT, int EPT, bool PACKED, bool CHECK, bool RTN, bool REPL, bool WIN, bool ERR>
 __device__ __forceinline__ Part eval_fast(const float (&u)[EPT], const float (&xv)[EPT],
                                           const float (&wv)[EPT], int n, int tid, float P, float Ss,
-                                          float Z, uint32_t* hist, int base, int rl, int cpy,
-                                          const double* lf, uint32_t& ovf) {
+                                          float Z, uint32_t* hist, int base, int lo, int nwords, int rl,
+                                          int cpy, const double* lf, uint32_t& seen) {
     const float M = 8388608.0f;  // 2^23
     const float MZ = M + Z;
     const float hi = M + (P - 1.0f);
     Part acc{0.0f, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        if (CHECK && i * NT + tid >= n) continue;
+        const bool valid = !CHECK || i * NT + tid < n;
+        if (!WIN && !valid) continue;
         float t = __builtin_fmaf(u[i], P, Z);
         float tm = __builtin_amdgcn_fmed3f(t + M, M, hi);
         uint32_t qi = __float_as_uint(tm) - 0x4B000000u;
+        int word;
+        uint32_t sh = 0;
         if (PACKED) {
-            const uint32_t sh = (qi & 1u) << 4;
-            const uint32_t old = atomicAdd(&hist[base + (int)(qi >> 1)], 1u << sh);
-            if (RTN) add_increment((old >> sh) & 0xFFFFu, lf, acc, ovf);
+            word = (int)(qi >> 1);
+            sh = (qi & 1u) << 4;
         } else {
-            const int word = REPL ? (((int)qi << rl) | cpy) : (int)qi;
-            const uint32_t old = atomicAdd(&hist[base + word], 1u);
-            if (RTN) add_increment(old, lf, acc, ovf);
+            word = REPL ? (((int)qi << rl) | cpy) : (int)qi;
         }
-        float xh = (tm - MZ) * Ss;
-        float d = xh - xv[i];
-        acc.err = __builtin_fmaf(wv[i], d * d, acc.err);
+        if (!WIN || (valid && (uint32_t)(word - lo) < (uint32_t)nwords)) {
+            const uint32_t old = atomicAdd(&hist[base + word], 1u << sh);
+            if (RTN) {
+                add_increment(old >> sh, lf, acc);
+                seen |= old;
+            }
+        }
+        if (ERR) {
+            float xh = (tm - MZ) * Ss;
+            float d = xh - xv[i];
+            acc.err = __builtin_fmaf(wv[i], d * d, acc.err);
+        }
     }
     return acc;
 }
 
-// The same pass for the rare cases, with runtime switches: bins split into
-// windows, |Z| > 2^23 (rint path) or the literal division per element.
+// The same pass for the rare cases, with runtime switches: |Z| > 2^23 (rint
+// path) or the literal division per element, bins possibly in windows.
 // Literal tiles are never scaled (E = 0, Ss = S) and keep the loss in FP64.
 template <int NT, int EPT>
 __device__ __forceinline__ Part eval_generic(const float (&u)[EPT], const float (&xv)[EPT],
                                              const float (&wv)[EPT], int n, int tid, float P, float S,
                                              float Ss, float Z, uint32_t* hist, int base, int lo,
                                              int nwords, bool packed, int rl, int cpy, bool literal,
-                                             bool err, bool rtn, const double* lf, uint32_t& ovf) {
+                                             bool err, bool rtn, const double* lf, uint32_t& seen) {
     const float qmax = P - 1.0f;
     Part acc{0.0f, 0.0, 0.0};
 #pragma unroll
@@ -169,7 +191,10 @@ __device__ __forceinline__ Part eval_generic(const float (&u)[EPT], const float 
         uint32_t sh = packed ? ((qi & 1u) << 4) : 0u;
         if ((uint32_t)(word - lo) < (uint32_t)nwords) {
             uint32_t old = atomicAdd(&hist[base + word], 1u << sh);
-            if (rtn) add_increment((old >> sh) & 0xFFFFu, lf, acc, ovf);
+            if (rtn) {
+                add_increment(old >> sh, lf, acc);
+                seen |= old;
+            }
         }
         if (err) {
             float xh = (q - Z) * Ss;
@@ -185,25 +210,57 @@ __device__ __forceinline__ Part eval_generic(const float (&u)[EPT], const float 
     return acc;
 }
 
+// FP64 loss of one non-literal pass, recomputed from the registers (the same
+// codes and FP32 dequantized values as the pass, exact FP64 differences);
+// used when the FP32 sum of a wavefront cannot be trusted.
+template <int NT, int EPT>
+__device__ __forceinline__ double loss_f64(const float (&u)[EPT], const float (&xv)[EPT],
+                                        const float (&wv)[EPT], int n, int tid, float P, float Ss,
+                                        float Z) {
+    const float qmax = P - 1.0f;
+    double e = 0.0;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        if (i * NT + tid >= n) continue;
+        float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(u[i], P, Z), 0.0f, qmax);
+        float xh = (__builtin_rintf(t) - Z) * Ss;
+        double d = (double)xh - (double)xv[i];
+        e = __builtin_fma((double)wv[i], d * d, e);
+    }
+    return e;
+}
+
 template <int NT, int EPT, bool PACKED>
-__device__ __forceinline__ Part eval_fast_dispatch(bool check, bool rtn, int rl, int cpy,
+__device__ __forceinline__ Part eval_fast_dispatch(bool check, bool rtn, bool win, bool err, int lo,
+                                                   int nwords, int rl, int cpy,
                                                    const float (&u)[EPT], const float (&xv)[EPT],
                                                    const float (&wv)[EPT], int n, int tid, float P,
-                                                   float S, float Z, uint32_t* hist, int base,
-                                                   const double* lf, uint32_t& ovf) {
-#define MGS_EVAL(CHK, RT, RP) \
-    eval_fast<NT, EPT, PACKED, CHK, RT, RP>(u, xv, wv, n, tid, P, S, Z, hist, base, rl, cpy, lf, ovf)
+                                                   float Ss, float Z, uint32_t* hist, int base,
+                                                   const double* lf, uint32_t& seen) {
+#define MGS_EVAL(CHK, RT, RP, WN, ER)                                                              \
+    eval_fast<NT, EPT, PACKED, CHK, RT, RP, WN, ER>(u, xv, wv, n, tid, P, Ss, Z, hist, base, lo, \
+                                                    nwords, rl, cpy, lf, seen)
     if constexpr (PACKED) {
-        if (check) return rtn ? MGS_EVAL(true, true, false) : MGS_EVAL(true, false, false);
-        return rtn ? MGS_EVAL(false, true, false) : MGS_EVAL(false, false, false);
+        // bin windows only occur on packed histograms; the loss is summed in
+        // the first window of a bit-width
+        if (win) {
+            if (check) {
+                if (rtn) return err ? MGS_EVAL(true, true, false, true, true) : MGS_EVAL(true, true, false, true, false);
+                return err ? MGS_EVAL(true, false, false, true, true) : MGS_EVAL(true, false, false, true, false);
+            }
+            if (rtn) return err ? MGS_EVAL(false, true, false, true, true) : MGS_EVAL(false, true, false, true, false);
+            return err ? MGS_EVAL(false, false, false, true, true) : MGS_EVAL(false, false, false, true, false);
+        }
+        if (check) return rtn ? MGS_EVAL(true, true, false, false, true) : MGS_EVAL(true, false, false, false, true);
+        return rtn ? MGS_EVAL(false, true, false, false, true) : MGS_EVAL(false, false, false, false, true);
     } else {
         // replicated bins only ever appear on scanned (non-incremental) entries
         if (check) {
-            if (rtn) return MGS_EVAL(true, true, false);
-            return rl ? MGS_EVAL(true, false, true) : MGS_EVAL(true, false, false);
+            if (rtn) return MGS_EVAL(true, true, false, false, true);
+            return rl ? MGS_EVAL(true, false, true, false, true) : MGS_EVAL(true, false, false, false, true);
         }
-        if (rtn) return MGS_EVAL(false, true, false);
-        return rl ? MGS_EVAL(false, false, true) : MGS_EVAL(false, false, false);
+        if (rtn) return MGS_EVAL(false, true, false, false, true);
+        return rl ? MGS_EVAL(false, false, true, false, true) : MGS_EVAL(false, false, false, false, true);
     }
 #undef MGS_EVAL
 }
@@ -223,7 +280,7 @@ void sweep_kernel(SweepParams p) {
     __shared__ double lf[LGTAB];
     __shared__ double errpart[MGS_MAX_BITS][NW];
     __shared__ double bitpart[MGS_MAX_BITS][NW];
-    __shared__ float red_mn[NW], red_mx[NW];
+    __shared__ float red_mn[NW], red_mx[NW], red_w[NW];
     __shared__ uint32_t red_bad[NW];
     __shared__ float prmS[MGS_MAX_BITS], prmZ[MGS_MAX_BITS];
 
@@ -235,10 +292,11 @@ void sweep_kernel(SweepParams p) {
     const double* __restrict__ lft = p.lgtab + (p.lgtab_max + 1);
     for (int h = tid; h < LGTAB; h += NT) {
         lg[h] = h <= p.lgtab_max ? lgt[h] : 0.0;
-        lf[h] = (h <= p.lgtab_max && h < LGTAB - 1) ? lft[h] : 0.0;
+        lf[h] = h <= p.lgtab_max ? lft[h] : 0.0;
     }
-    // grid value of T(LGTAB - 1), the start of every correction
-    const double rt_top = grid_round(lgt[min(LGTAB - 1, p.lgtab_max)], p.kgrid);
+    // grid value of T(LGTAB), what one full cycle of the LDS increments adds
+    // up to (only counts above LGTAB need it)
+    const double rt_cycle = p.lgtab_max >= LGTAB ? grid_round(lgt[LGTAB], p.kgrid) : 0.0;
 
     for (int64_t it = blockIdx.x; it < p.ntiles; it += gridDim.x) {
         // ---- locate the tile: scene, then (channel run, ratio t, group g);
@@ -282,7 +340,7 @@ void sweep_kernel(SweepParams p) {
             asm volatile("" : "+v"(Jc), "+v"(impc));
             const float* row = sc->attr + (int64_t)c * sc->ld;
             const int64_t slot = ((int64_t)t * sc->C + c) * sc->gmaxn + g;
-            float mn = INFINITY, mx = -INFINITY;
+            float mn = INFINITY, mx = -INFINITY, wm = 0.0f;  // wm: largest |weight|
             uint32_t bad = 0;
             auto gather = [&](int ch) {
 #pragma unroll
@@ -296,6 +354,7 @@ void sweep_kernel(SweepParams p) {
                         bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
                         mn = fminf(mn, x);
                         mx = fmaxf(mx, x);
+                        wm = fmaxf(wm, fabsf(w));
                     }
                     xv[i] = x;
                     wv[i] = w;
@@ -308,20 +367,24 @@ void sweep_kernel(SweepParams p) {
             }
             mn = wave_min_f32(mn);
             mx = wave_max_f32(mx);
+            wm = wave_max_f32(wm);
             bad = wave_or_u32(bad);
             if (lane == 0) {
                 red_mn[wave] = mn;
                 red_mx[wave] = mx;
+                red_w[wave] = wm;
                 red_bad[wave] = bad;
             }
             __syncthreads();
             mn = red_mn[0];
             mx = red_mx[0];
+            wm = red_w[0];
             bad = red_bad[0];
 #pragma unroll
             for (int w = 1; w < NW; ++w) {
                 mn = fminf(mn, red_mn[w]);
                 mx = fmaxf(mx, red_mx[w]);
+                wm = fmaxf(wm, red_w[w]);
                 bad |= red_bad[w];
             }
             const float R = mx - mn;
@@ -419,21 +482,37 @@ void sweep_kernel(SweepParams p) {
                                     }
                                 }
                             }
-                        } else if (fast && !en.split && fabsf(Z) <= 8388608.0f) {
+                        } else if (fast && fabsf(Z) <= 8388608.0f && (en.packed || !en.split)) {
+                            uint32_t seen = 0;
                             if (en.packed)
-                                acc = eval_fast_dispatch<NT, EPT, true>(check, en.rtn, 0, 0, u, xv, wv, nc,
-                                                                        tid, P, Ss, Z, hist, base, lf, ovf);
+                                acc = eval_fast_dispatch<NT, EPT, true>(check, en.rtn, en.split, en.first, en.lo,
+                                                                        en.nwords, 0, 0, u, xv, wv, nc, tid, P,
+                                                                        Ss, Z, hist, base, lf, seen);
                             else
-                                acc = eval_fast_dispatch<NT, EPT, false>(check, en.rtn, rl, cpy, u, xv, wv,
-                                                                         nc, tid, P, Ss, Z, hist, base, lf,
-                                                                         ovf);
+                                acc = eval_fast_dispatch<NT, EPT, false>(check, en.rtn, false, true, 0, 0, rl,
+                                                                         cpy, u, xv, wv, nc, tid, P, Ss, Z,
+                                                                         hist, base, lf, seen);
+                            ovf |= seen & big_count_mask(en.packed);
                         } else {
+                            uint32_t seen = 0;
                             acc = eval_generic<NT, EPT>(u, xv, wv, nc, tid, P, S, Ss, Z, hist, base, en.lo,
                                                         en.nwords, en.packed, rl, cpy, !fast, en.first,
-                                                        en.rtn, lf, ovf);
+                                                        en.rtn, lf, seen);
+                            ovf |= seen & big_count_mask(en.packed);
                         }
                         if (en.first) {
-                            const double tot = wave_total_f64((double)acc.err * esc + acc.err64);
+                            double tot;
+                            if (fast && S != 0.0f) {
+                                // FP32 terms (scaled by 2^-2E): trusted when finite and
+                                // large enough that underflowed terms cannot matter
+                                const float t32 = wave_total_f32(acc.err);
+                                if (__builtin_isfinite(t32) && t32 >= (wm + 1.0f) * 0x1p-112f)
+                                    tot = (double)t32 * esc;
+                                else
+                                    tot = wave_total_f64(loss_f64<NT, EPT>(u, xv, wv, nc, tid, P, Ss, Z)) * esc;
+                            } else {
+                                tot = wave_total_f64(acc.err64);
+                            }
                             if (lane == 0) errpart[bi][wave] += tot;
                         }
                         if (en.rtn && S != 0.0f) {
@@ -444,9 +523,10 @@ void sweep_kernel(SweepParams p) {
                 }
                 const bool any_ovf = __syncthreads_or((int)ovf) != 0;
                 // ---- entropy terms of the scanned histograms, the corrections
-                // of incremental ones whose bins outgrew the LDS table (each such
-                // bin got T(LGTAB - 1) from the increments and needs T(h) on the
-                // same grid), and the optional debug copy of the bins
+                // of incremental ones whose bins outgrew the LDS table (a bin of
+                // h > LGTAB got floor(h / LGTAB) full cycles of the increments plus
+                // the first h mod LGTAB of them, and needs R(T(h)) on the same
+                // grid), and the optional debug copy of the bins
                 for (int e = e0; e < e1; ++e) {
                     const HistEntry en = p.entries[e];
                     const bool scan = !en.rtn || prmS[en.bi] == 0.0f;
@@ -456,7 +536,9 @@ void sweep_kernel(SweepParams p) {
                     double s = 0.0;
                     auto term = [&](uint32_t h) {
                         if (scan) s += hlog2h(h, lg, lgt);
-                        else if (fix && h >= (uint32_t)(LGTAB - 1)) s += grid_round(lgt[h], p.kgrid) - rt_top;
+                        else if (fix && h > (uint32_t)LGTAB)
+                            s += grid_round(lgt[h], p.kgrid) - (double)(h / LGTAB) * rt_cycle -
+                                 grid_round(lg[h % LGTAB], p.kgrid);
                     };
                     if (en.rlog) {
                         // replicated bins: the 2^rlog copies of a bin sit in adjacent
@@ -623,7 +705,7 @@ int device_cus() {
 // Static LDS of a kernel variant (everything but the histogram words).
 static int static_lds_bytes(int nt) {
     int nw = nt / MGS_WAVE;
-    return (int)(2 * sizeof(double) * LGTAB + 2 * sizeof(double) * MGS_MAX_BITS * nw + 3 * 4 * nw +
+    return (int)(2 * sizeof(double) * LGTAB + 2 * sizeof(double) * MGS_MAX_BITS * nw + 4 * 4 * nw +
                  2 * 4 * MGS_MAX_BITS) + 256;
 }
 
