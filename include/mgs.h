@@ -93,9 +93,12 @@ int mgs_prune_select(const float* d_imp, int64_t n, const int64_t* h_k, int32_t 
  * histograms, uint32 [T][C][Gmax][sum_i 2^bits[i]] (2^b bins per listed b,
  * in list order); meant for small inputs.  Codes, histograms and group
  * bounds are exact.  err: each thread sums the FP32 terms of at most 32
- * elements before an FP64 reduction, so it agrees with the FP64 definition
- * within 35 * 2^-24 (~2.1e-6) relative (groups that need the literal
- * division or whose step underflows keep FP64 terms).  bits: FP64 entropy,
+ * elements, a wavefront sums its 64 threads in FP32, and the wavefront
+ * totals are added in FP64, so for nonnegative weights it agrees with the
+ * FP64 definition within 41 * 2^-24 (~2.4e-6) relative; a wavefront total
+ * that overflows, or is small enough that underflowed terms could matter,
+ * is recomputed with FP64 terms, as are groups that need the literal
+ * division or whose step underflows.  bits: FP64 entropy,
  * within ~1e-12 relative plus G * 2^-(K+1) absolute where the entropy comes
  * from grid-rounded increments (K = 52 - ceil(log2(G log2 G + G + 1))).
  * Results are deterministic: the same inputs give bit-identical tables.
