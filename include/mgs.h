@@ -102,6 +102,9 @@ int mgs_prune_select(const float* d_imp, int64_t n, const int64_t* h_k, int32_t 
  * within ~1e-12 relative plus G * 2^-(K+1) absolute where the entropy comes
  * from grid-rounded increments (K = 52 - ceil(log2(G log2 G + G + 1))).
  * Results are deterministic: the same inputs give bit-identical tables.
+ * Workspace: mgs_quant_sweep_ws_bytes(desc) bytes, which grow with
+ * sum_t ceil(k_t / G) (one int per group for the tile order); a descriptor
+ * with h_k == NULL gets the bound for T ratios of N Gaussians each.
  * Limits: 1 <= G <= MGS_MAX_GROUP, 1 <= T <= MGS_MAX_RATIOS, h_bits strictly
  * increasing in [1, 16], ld >= N, 0 <= k_t <= N, kept indices in [0, N).
  * Errors: MGS_EINVAL, MGS_EWORKSPACE; non-finite attributes or weights in a
@@ -130,8 +133,9 @@ int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float
  * list) in one launch; every table equals what mgs_quant_sweep computes for
  * that scene alone, bit for bit.  h_jobs (host, njobs entries) is read
  * during the call only.  The workspace (mgs_quant_sweep_multi_ws_bytes,
- * which depends on njobs and G) carries one status word for the whole
- * launch.  Errors: as mgs_quant_sweep, plus MGS_EINVAL when njobs is outside
+ * which depends on njobs, G and every job's group count, bounded as in
+ * mgs_quant_sweep_ws_bytes for jobs whose h_k is NULL) carries one status
+ * word for the whole launch.  Errors: as mgs_quant_sweep, plus MGS_EINVAL when njobs is outside
  * [1, MGS_MAX_JOBS] or the jobs differ in G or the bit-width list.
  */
 typedef struct {

@@ -9,6 +9,7 @@ constexpr int LGTAB = 256;            // h * log2(h) table entries kept in LDS
 constexpr int MGS_MAX_ENTRIES = 40;   // histogram windows per plan
 constexpr int REPL_WORDS = 1024;      // words a replicated low-b histogram may take
 constexpr int REPL_MAX_LOG = 5;       // at most 32 copies per bin
+constexpr int MGS_XCDS = 8;           // XCDs that workgroups are dispatched over, round-robin
 
 // One histogram window of one bit-width inside a batch of LDS words.
 struct HistEntry {
@@ -34,6 +35,7 @@ struct SceneDesc {
     float* gmin;
     float* gmax;
     uint32_t* hist;
+    int32_t* order;                 // [gpc]: the run's groups in tile order (workspace)
     int64_t ld;
     int64_t hist_bins;              // sum over the list of 2^b
     int32_t C, T, G, nb;
@@ -82,7 +84,8 @@ int plan_for(const SceneDesc& sc, const Shape& sh, SweepParams* p, size_t* lds_b
 Shape default_shape(int G, int nb, int bmax);
 bool shape_valid(const Shape& sh, int G);
 // Copies `count` scene descriptors into device memory and prepares the
-// tables (NaN padding, status reset, debug histogram clearing).
+// tables (NaN padding, status reset, debug histogram clearing) and each
+// scene's tile order (host_scenes[i].order must point at gpc ints).
 int launch_init(const SceneDesc* host_scenes, int count, SceneDesc* d_scenes,
                 mgs_status_block* status, double* lgtab, int lgtab_max, hipStream_t s);
 // Grid exponent K of the entropy increments: every partial sum of up to G

@@ -111,6 +111,19 @@ __device__ __forceinline__ uint32_t big_count_mask(bool packed) {
     return packed ? 0xFF00FF00u : 0xFFFFFF00u;
 }
 
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// LDS byte address of a shared-memory word (LDS addresses are 32-bit).
+__device__ __forceinline__ uint32_t lds_addr(const uint32_t* p) {
+    return (uint32_t)(uintptr_t)(const lds_u32*)p;
+}
+
+// Atomic add to the LDS word at byte address `addr`; returns the old value.
+__device__ __forceinline__ uint32_t lds_add(uint32_t addr, uint32_t v) {
+    return __hip_atomic_fetch_add((lds_u32*)(uintptr_t)addr, v, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // One histogram pass over the tile's elements for one bit-width on the fast
 // path (x / S_b from x / R, 2^23 rounding trick), specialised on packed bins,
 // ragged group, incremental entropy (RTN: the atomic's old count c gives
@@ -118,19 +131,28 @@ __device__ __forceinline__ uint32_t big_count_mask(bool packed) {
 // bins, a bin window and whether the pass also sums the loss.
 // xv holds x * 2^-E and Ss = S * 2^-E: both scalings are exact, so the
 // dequantized value (q - Z) * Ss is exactly xhat * 2^-E.
+// Bin addresses come straight from the bits of tm = 2^23 + q, which are
+// 0x4B000000 + q: with the per-entry constant cadj (LDS base of the bins,
+// replica lane, minus the shifted 0x4B000000; kept opaque so that the
+// compiler does not re-associate it) the byte address of bin word
+// (q << rl) | cpy is (bits << (rl + 2)) + cadj, one shift-add; packed bins
+// (word q >> 1, half q & 1) use ((bits << 1) + cadj) & ~3 and the half's
+// shift 16 * (q & 1) = (bits << 4) mod 32.
 // REPL: 2^rl copies of every bin, bin q of lane l in word (q << rl) | cpy with
 // cpy = l mod 2^rl, so lanes that share a bin hit different LDS banks.
-// WIN: only words [lo, lo + nwords) live in LDS this pass; elements past the
-// ragged end carry w = 0 and x = 0, so they add nothing to the loss.
+// WIN: only the words at byte addresses [wlo, wlo + wbytes) live in LDS this
+// pass; elements past the ragged end carry w = 0 and x = 0, so they add
+// nothing to the loss.
 // Returns the OR of the counters the pass read (RTN) in `seen`.
 template <int NT, int EPT, bool PACKED, bool CHECK, bool RTN, bool REPL, bool WIN, bool ERR>
 __device__ __forceinline__ Part eval_fast(const float (&u)[EPT], const float (&xv)[EPT],
                                           const float (&wv)[EPT], int n, int tid, float P, float Ss,
-                                          float Z, uint32_t* hist, int base, int lo, int nwords, int rl,
-                                          int cpy, const double* lf, uint32_t& seen) {
+                                          float Z, uint32_t cadj, uint32_t wlo, uint32_t wbytes, int rl,
+                                          const double* lf, uint32_t& seen) {
     const float M = 8388608.0f;  // 2^23
     const float MZ = M + Z;
     const float hi = M + (P - 1.0f);
+    const uint32_t shl = REPL ? (uint32_t)rl + 2u : 2u;
     Part acc{0.0f, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -138,19 +160,19 @@ __device__ __forceinline__ Part eval_fast(const float (&u)[EPT], const float (&x
         if (!WIN && !valid) continue;
         float t = __builtin_fmaf(u[i], P, Z);
         float tm = __builtin_amdgcn_fmed3f(t + M, M, hi);
-        uint32_t qi = __float_as_uint(tm) - 0x4B000000u;
-        int word;
-        uint32_t sh = 0;
+        const uint32_t tb = __float_as_uint(tm);
+        uint32_t addr, inc = 1u, sh = 0u;
         if (PACKED) {
-            word = (int)(qi >> 1);
-            sh = (qi & 1u) << 4;
+            addr = ((tb << 1) + cadj) & ~3u;
+            sh = (tb << 4) & 31u;
+            inc = 1u << sh;
         } else {
-            word = REPL ? (((int)qi << rl) | cpy) : (int)qi;
+            addr = (tb << shl) + cadj;
         }
-        if (!WIN || (valid && (uint32_t)(word - lo) < (uint32_t)nwords)) {
-            const uint32_t old = atomicAdd(&hist[base + word], 1u << sh);
+        if (!WIN || (valid && addr - wlo < wbytes)) {
+            const uint32_t old = lds_add(addr, inc);
             if (RTN) {
-                add_increment(old >> sh, lf, acc);
+                acc.ent += lf[PACKED ? __builtin_amdgcn_ubfe(old, sh, 8) : (old & (uint32_t)(LGTAB - 1))];
                 seen |= old;
             }
         }
@@ -231,15 +253,14 @@ __device__ __forceinline__ double loss_f64(const float (&u)[EPT], const float (&
 }
 
 template <int NT, int EPT, bool PACKED>
-__device__ __forceinline__ Part eval_fast_dispatch(bool check, bool rtn, bool win, bool err, int lo,
-                                                   int nwords, int rl, int cpy,
+__device__ __forceinline__ Part eval_fast_dispatch(bool check, bool rtn, bool win, bool err,
+                                                   uint32_t cadj, uint32_t wlo, uint32_t wbytes, int rl,
                                                    const float (&u)[EPT], const float (&xv)[EPT],
                                                    const float (&wv)[EPT], int n, int tid, float P,
-                                                   float Ss, float Z, uint32_t* hist, int base,
-                                                   const double* lf, uint32_t& seen) {
+                                                   float Ss, float Z, const double* lf, uint32_t& seen) {
 #define MGS_EVAL(CHK, RT, RP, WN, ER)                                                              \
-    eval_fast<NT, EPT, PACKED, CHK, RT, RP, WN, ER>(u, xv, wv, n, tid, P, Ss, Z, hist, base, lo, \
-                                                    nwords, rl, cpy, lf, seen)
+    eval_fast<NT, EPT, PACKED, CHK, RT, RP, WN, ER>(u, xv, wv, n, tid, P, Ss, Z, cadj, wlo, wbytes, \
+                                                    rl, lf, seen)
     if constexpr (PACKED) {
         // bin windows only occur on packed histograms; the loss is summed in
         // the first window of a bit-width
@@ -290,6 +311,7 @@ void sweep_kernel(SweepParams p) {
 
     const double* __restrict__ lgt = p.lgtab;
     const double* __restrict__ lft = p.lgtab + (p.lgtab_max + 1);
+    const uint32_t hist_lds = lds_addr(hist);
     for (int h = tid; h < LGTAB; h += NT) {
         lg[h] = h <= p.lgtab_max ? lgt[h] : 0.0;
         lf[h] = h <= p.lgtab_max ? lft[h] : 0.0;
@@ -298,9 +320,22 @@ void sweep_kernel(SweepParams p) {
     // up to (only counts above LGTAB need it)
     const double rt_cycle = p.lgtab_max >= LGTAB ? grid_round(lgt[LGTAB], p.kgrid) : 0.0;
 
-    for (int64_t it = blockIdx.x; it < p.ntiles; it += gridDim.x) {
-        // ---- locate the tile: scene, then (channel run, ratio t, group g);
-        // channels [c0, c1)
+    // Workgroups are dispatched round-robin over the XCDs: give each XCD a
+    // contiguous run of tiles, so that one XCD's L2 serves the neighbouring
+    // groups of every ratio (a grid that is not a multiple of the XCD count
+    // strides plainly).
+    int64_t it0 = blockIdx.x, step = gridDim.x, it_end = p.ntiles;
+    if (gridDim.x % MGS_XCDS == 0) {
+        const int64_t per = (p.ntiles + MGS_XCDS - 1) / MGS_XCDS;
+        const int x = (int)(blockIdx.x % MGS_XCDS);
+        it0 = (int64_t)x * per + blockIdx.x / MGS_XCDS;
+        step = gridDim.x / MGS_XCDS;
+        it_end = min(p.ntiles, (int64_t)(x + 1) * per);
+    }
+    for (int64_t it = it0; it < it_end; it += step) {
+        // ---- locate the tile: scene, then (channel run, ratio t, group g)
+        // with the run's groups taken in the scene's tile order; channels
+        // [c0, c1)
         int sid = 0;
         while (sid + 1 < p.nscenes && p.tcum[sid + 1] <= it) ++sid;
         const SceneDesc* sc = &p.scenes[sid];
@@ -309,7 +344,7 @@ void sweep_kernel(SweepParams p) {
             const int64_t lt = it - p.tcum[sid];
             const int64_t gpc = sc->gpc;
             const int cc = (int)(lt / gpc);
-            const int r = (int)(lt - (int64_t)cc * gpc);
+            const int r = sc->order[(int)(lt - (int64_t)cc * gpc)];
             c0 = cc * p.cpb;
             t = 0;
             while (t + 1 < sc->T && sc->gcum[t + 1] <= r) ++t;
@@ -484,14 +519,21 @@ void sweep_kernel(SweepParams p) {
                             }
                         } else if (fast && fabsf(Z) <= 8388608.0f && (en.packed || !en.split)) {
                             uint32_t seen = 0;
+                            // byte address of bin word w: base + w, in the 0x4B000000-biased
+                            // form the fast path uses (see eval_fast)
+                            const uint32_t wlo = hist_lds + 4u * (uint32_t)en.lds_off;
+                            uint32_t cadj = en.packed
+                                                ? hist_lds + 4u * (uint32_t)base - (0x4B000000u << 1)
+                                                : hist_lds + 4u * (uint32_t)(base + cpy) - (0x4B000000u << (rl + 2));
+                            asm volatile("" : "+v"(cadj));
                             if (en.packed)
-                                acc = eval_fast_dispatch<NT, EPT, true>(check, en.rtn, en.split, en.first, en.lo,
-                                                                        en.nwords, 0, 0, u, xv, wv, nc, tid, P,
-                                                                        Ss, Z, hist, base, lf, seen);
+                                acc = eval_fast_dispatch<NT, EPT, true>(check, en.rtn, en.split, en.first, cadj, wlo,
+                                                                        4u * (uint32_t)en.nwords, 0, u, xv, wv, nc,
+                                                                        tid, P, Ss, Z, lf, seen);
                             else
-                                acc = eval_fast_dispatch<NT, EPT, false>(check, en.rtn, false, true, 0, 0, rl,
-                                                                         cpy, u, xv, wv, nc, tid, P, Ss, Z,
-                                                                         hist, base, lf, seen);
+                                acc = eval_fast_dispatch<NT, EPT, false>(check, en.rtn, false, true, cadj, wlo,
+                                                                         4u * (uint32_t)en.nwords, rl, u, xv, wv,
+                                                                         nc, tid, P, Ss, Z, lf, seen);
                             ovf |= seen & big_count_mask(en.packed);
                         } else {
                             uint32_t seen = 0;
@@ -599,9 +641,41 @@ __global__ void scene_copy_kernel(SceneDesc sd, SceneDesc* dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = sd;
 }
 
+// Position of group g of ratio t along the Gaussian index: the middle of its
+// run of kept positions as a fraction of k_t.  Kept indices ascend, so groups
+// of different ratios at similar positions read nearby Gaussians.
+__device__ __forceinline__ double group_pos(const SceneDesc* sc, int t, int g) {
+    const int64_t j0 = (int64_t)g * sc->G;
+    const int64_t n = min((int64_t)sc->G, sc->k[t] - j0);
+    return (double)(2 * j0 + n) / (double)(2 * sc->k[t]);
+}
+
+// Tile order of a channel run: its groups sorted by (position, ratio).  The
+// rank of group (t, g) counts, per ratio, the groups before it (positions
+// increase with g, so a binary search per ratio); order[rank] = r.
+__device__ void tile_order(SceneDesc* sc, int r) {
+    int t = 0;
+    while (t + 1 < sc->T && sc->gcum[t + 1] <= r) ++t;
+    const int g = r - sc->gcum[t];
+    const double pos = group_pos(sc, t, g);
+    int rank = g;
+    for (int u = 0; u < sc->T; ++u) {
+        if (u == t) continue;
+        int lo = 0, hi = sc->gcum[u + 1] - sc->gcum[u];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const double pm = group_pos(sc, u, mid);
+            if (pm < pos || (pm == pos && u < t)) lo = mid + 1;
+            else hi = mid;
+        }
+        rank += lo;
+    }
+    sc->order[rank] = r;
+}
+
 // Empty slots (groups past ceil(k_t / G)) hold NaN; the debug histogram is
-// cleared; the status word is reset.
-__global__ void sweep_init_kernel(const SceneDesc* __restrict__ scenes, int count,
+// cleared; the status word is reset; every scene gets its tile order.
+__global__ void sweep_init_kernel(SceneDesc* __restrict__ scenes, int count,
                                   mgs_status_block* status, double* lgtab, int lgtab_max, int K) {
     if (blockIdx.x == 0 && threadIdx.x == 0) status->nonfinite = 0u;
     // T(h) = h log2 h for every count a group can hold (FP64, 0 for h < 2),
@@ -616,7 +690,9 @@ __global__ void sweep_init_kernel(const SceneDesc* __restrict__ scenes, int coun
         inc[h] = grid_round(t1, K) - grid_round(t0, K);
     }
     for (int s = 0; s < count; ++s) {
-        const SceneDesc* sc = &scenes[s];
+        SceneDesc* sc = &scenes[s];
+        for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < sc->gpc; r += gridDim.x * blockDim.x)
+            tile_order(sc, r);
         const int64_t nslot = (int64_t)sc->T * sc->C * sc->gmaxn;
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslot;
              i += (int64_t)gridDim.x * blockDim.x) {
@@ -871,8 +947,10 @@ int launch_sweep(const SweepParams& p, const Shape& sh, size_t lds,
                  int64_t grid, hipStream_t s, int G) {
     const Variant* v = find_variant(sh.nt, sh.ept, G);
     if (!v) return MGS_EINVAL;
-    if (grid <= 0 || grid > p.ntiles) grid = p.ntiles;
-    if (grid < 1) return MGS_OK;
+    // one workgroup per tile, rounded up to whole XCD rounds (the extra
+    // workgroups find no tile)
+    if (grid <= 0 || grid > p.ntiles) grid = (p.ntiles + MGS_XCDS - 1) / MGS_XCDS * MGS_XCDS;
+    if (p.ntiles < 1) return MGS_OK;
     if (grid > 0x7fffffff) grid = 0x7fffffff;
     return v->fn(p, grid, lds, s) == hipSuccess ? MGS_OK : MGS_EDEVICE;
 }
@@ -941,30 +1019,49 @@ void set_tuned_shape(int G, int nb, int bmax, const Shape& sh) {
 
 // ------------------------------------------------------------------ C ABI
 
-// Workspace: status word | scene descriptor | h log2 h table [0, G] |
-// entropy increments [0, G].
 // Workspace: status word | scene descriptors | h log2 h table [0, G] |
-// entropy increments [0, G].
+// entropy increments [0, G] | each scene's tile order (one int per group of
+// a channel run).
 static size_t sweep_ws_scene_off() { return MGS_STATUS_BYTES; }
 static size_t sweep_ws_table_off(int nscenes) {
     return sweep_ws_scene_off() + mgs_align_up(sizeof(mgs::SceneDesc) * (size_t)nscenes, 256);
 }
-static size_t sweep_ws_bytes(int nscenes, int G) {
-    if (G < 1 || G > MGS_MAX_GROUP) G = MGS_MAX_GROUP;
-    return sweep_ws_table_off(nscenes) + mgs_align_up(2 * sizeof(double) * ((size_t)G + 1), 256);
+static int sweep_ws_clamp_g(int G) { return (G < 1 || G > MGS_MAX_GROUP) ? MGS_MAX_GROUP : G; }
+static size_t sweep_ws_order_off(int nscenes, int G) {
+    return sweep_ws_table_off(nscenes) +
+           mgs_align_up(2 * sizeof(double) * ((size_t)sweep_ws_clamp_g(G) + 1), 256);
+}
+static size_t sweep_ws_bytes(int nscenes, int G, int64_t groups) {
+    return sweep_ws_order_off(nscenes, G) + mgs_align_up(sizeof(int32_t) * (size_t)groups, 256);
+}
+
+// Groups per channel run of a descriptor: sum_t ceil(k_t / G), or the bound
+// T * ceil(N / G) when the counts are not given.
+static int64_t sweep_desc_groups(const mgs_sweep_desc* d) {
+    if (!d || d->G < 1 || d->T < 1) return 0;
+    const int T = std::min<int>(d->T, MGS_MAX_RATIOS);
+    int64_t gc = 0;
+    if (d->h_k) {
+        for (int t = 0; t < T; ++t) gc += (std::max<int64_t>(d->h_k[t], 0) + d->G - 1) / d->G;
+    } else {
+        gc = (int64_t)T * ((std::max<int64_t>(d->N, 0) + d->G - 1) / d->G);
+    }
+    return gc;
 }
 
 extern "C" size_t mgs_quant_sweep_ws_bytes(const mgs_sweep_desc* desc) {
-    return sweep_ws_bytes(1, desc ? desc->G : MGS_MAX_GROUP);
+    return sweep_ws_bytes(1, desc ? desc->G : MGS_MAX_GROUP, sweep_desc_groups(desc));
 }
 
 extern "C" size_t mgs_quant_sweep_multi_ws_bytes(const mgs_sweep_job* h_jobs, int32_t njobs) {
-    if (!h_jobs || njobs < 1 || njobs > MGS_MAX_JOBS) return sweep_ws_bytes(MGS_MAX_JOBS, MGS_MAX_GROUP);
-    return sweep_ws_bytes(njobs, h_jobs[0].desc.G);
+    if (!h_jobs || njobs < 1 || njobs > MGS_MAX_JOBS) return sweep_ws_bytes(MGS_MAX_JOBS, MGS_MAX_GROUP, 0);
+    int64_t groups = 0;
+    for (int i = 0; i < njobs; ++i) groups += sweep_desc_groups(&h_jobs[i].desc);
+    return sweep_ws_bytes(njobs, h_jobs[0].desc.G, groups);
 }
 
 // One launch over the tiles of `n` scenes that share G and the bit list.
-static int sweep_launch_scenes(const mgs::SceneDesc* scs, int n, void* d_ws, size_t ws_bytes,
+static int sweep_launch_scenes(mgs::SceneDesc* scs, int n, void* d_ws, size_t ws_bytes,
                                hipStream_t s, const mgs::Shape* force) {
     using namespace mgs;
     if (n < 1 || n > MGS_MAX_JOBS) return MGS_EINVAL;
@@ -974,7 +1071,16 @@ static int sweep_launch_scenes(const mgs::SceneDesc* scs, int n, void* d_ws, siz
         for (int b = 0; b < s0.nb; ++b)
             if (scs[i].bl[b] != s0.bl[b]) return MGS_EINVAL;
     }
-    if (!d_ws || ws_bytes < sweep_ws_bytes(n, s0.G)) return MGS_EWORKSPACE;
+    int64_t groups = 0;
+    for (int i = 0; i < n; ++i) groups += scs[i].gpc;
+    if (!d_ws || ws_bytes < sweep_ws_bytes(n, s0.G, groups)) return MGS_EWORKSPACE;
+    {  // each scene's tile order in the workspace
+        int32_t* ord = (int32_t*)((char*)d_ws + sweep_ws_order_off(n, s0.G));
+        for (int i = 0; i < n; ++i) {
+            scs[i].order = ord;
+            ord += scs[i].gpc;
+        }
+    }
     Shape sh;
     if (force) {
         sh = *force;

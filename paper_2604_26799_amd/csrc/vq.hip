@@ -42,9 +42,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int VQ_WAVES = 4;
 constexpr int VQ_THREADS = VQ_WAVES * MGS_WAVE;
-constexpr int VQ_ROWSETS = 4;                          // 32-row sets per wave
+constexpr int VQ_ROWSETS = 2;                          // 32-row sets per wave
 constexpr int VQ_ROWS = VQ_WAVES * VQ_ROWSETS * 32;    // rows per workgroup
-constexpr int VQ_CHUNK = 128;                          // codewords per LDS chunk (two buffers)
+constexpr int VQ_CHUNK = 64;                           // codewords per LDS chunk (two buffers)
 constexpr int VQ_CAND = 8;                             // candidate tiles per lane and row set
 
 struct VqArgs {

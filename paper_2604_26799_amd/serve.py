@@ -153,9 +153,13 @@ class Server:
         self.launches = 0
         self.batch_sizes: List[int] = []
         # workspaces of the batched sweep, one per launch in flight (ring)
+        # (descriptors without counts: the size covers any job of up to store.n
+        # Gaussians and MAX_RATIOS reserve ratios)
         probe = (mgs.SweepJob * max_batch)()
         for j in range(max_batch):
             probe[j].desc.G = G
+            probe[j].desc.N = store.n
+            probe[j].desc.T = mgs.MAX_RATIOS
         need = mgs.lib().mgs_quant_sweep_multi_ws_bytes(probe, max_batch)
         self.ws_ring = [mgs.workspace(need, self.dev) for _ in range(8)]
         self.ws_next = 0

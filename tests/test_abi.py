@@ -122,6 +122,15 @@ def test_workspace_queries():
     assert L.mgs_vq_assign_ws_bytes(10, 0, 4) == 0
     d = mgs.sweep_desc(1000, 11, [500, 1000], 4096, [4, 5, 6])
     assert L.mgs_quant_sweep_ws_bytes(ct.byref(d)) >= 256 + 8 * 4097
+    # the tile order takes one int per group of a channel run
+    small = mgs.sweep_desc(10_000_000, 20, [1_000_000], 1024, [4, 8])
+    big = mgs.sweep_desc(10_000_000, 20, [1_000_000] * 8, 1024, [4, 8])
+    grow = L.mgs_quant_sweep_ws_bytes(ct.byref(big)) - L.mgs_quant_sweep_ws_bytes(ct.byref(small))
+    assert grow >= 4 * 7 * 977 and grow < 4 * 7 * 977 + 512
+    # without counts the size bounds every count vector of T ratios over N
+    nok = mgs.SweepDesc(10_000_000, 10_000_000, 20, 8, 1024, 2, None, None)
+    assert L.mgs_quant_sweep_ws_bytes(ct.byref(nok)) >= 4 * 8 * 9766
+    assert L.mgs_quant_sweep_ws_bytes(ct.byref(nok)) >= L.mgs_quant_sweep_ws_bytes(ct.byref(big))
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
