@@ -48,7 +48,7 @@
 // Literal-division groups and underflowed steps keep exact FP64 terms.
 // Size.  n log2 n - sum_k h_k log2 h_k in FP64.  Scanned histograms take
 // h log2 h per bin (LDS table for h < 256).  Histograms with more bins than
-// half the group instead add, per element, the increment of its bin's old
+// a sixteenth of the group instead add, per element, the increment of its bin's old
 // count c (returned by the atomic): F[c] = R(T(c+1)) - R(T(c)) with
 // T(h) = h log2 h and R the rounding to a 2^-K grid, so a bin's increments
 // telescope to R(T(h)) exactly and in any order.  The LDS copy of F covers
@@ -796,7 +796,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
     for (int i = 0; i < nb; ++i) {
         int full = 1 << bl[i];
         bool packed = full > cap_words;
-        bool rtn = (int64_t)2 << bl[i] > G;
+        bool rtn = (int64_t)16 << bl[i] > G;
         int rlog = 0;
         if (!packed && !rtn)
             while (rlog < REPL_MAX_LOG && (full << (rlog + 1)) <= std::min(REPL_WORDS, cap_words)) ++rlog;
@@ -814,7 +814,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
                 e.packed = it.packed;
                 e.first = lo == 0;
                 e.split = 1;
-                e.rtn = (int64_t)2 << bl[it.bi] > G;
+                e.rtn = (int64_t)16 << bl[it.bi] > G;
                 e.lo = lo;
                 e.nwords = std::min(cap_words, it.words - lo);
                 e.lds_off = 0;
@@ -836,9 +836,10 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         e.rlog = (uint8_t)it.rlog;
         e.first = 1;
         e.split = 0;
-        // more bins than half the elements: the entropy comes from the atomics'
-        // old counts, which is cheaper than scanning mostly-empty bins
-        e.rtn = (int64_t)2 << bl[it.bi] > G;
+        // more bins than a sixteenth of the elements: the entropy comes from the
+        // atomics' old counts, which is cheaper than scanning the bins (a scan
+        // costs a fixed latency-bound pass per bit-width; measured crossover)
+        e.rtn = (int64_t)16 << bl[it.bi] > G;
         e.lo = 0;
         e.nwords = it.words;
         e.lds_off = used[k];

@@ -9,7 +9,7 @@ of at most (32 + 9) * 2^-24 ~ 2.4e-6 (wavefront sums that overflow or could
 have lost terms to underflow are recomputed in FP64); the tests assert
 ERR_REL = 4e-6.  Literal-division and underflowed-step groups keep
 FP64 terms.  The size is the FP64 entropy; for bit-widths with more bins
-than half the group it comes from entropy increments on a 2^-K grid (exact
+than a sixteenth of the group it comes from entropy increments on a 2^-K grid (exact
 sums), which adds an absolute error of at most G * 2^-(K+1) bits (K from
 increment_bits below); the tests assert 1e-9 relative plus that bound.
 """
