@@ -271,6 +271,7 @@ def main():
                "mfma_frac": vq_flops / (med["vq"] * 1e-3) / MFMA_BF16_PEAK,
                "fallback_rows": int(nfb.item())},
     }
+    out["search_variants"] = search_variants(mgs, w, k, G, err_h.numpy(), bits_h.numpy(), budget_bits)
     if not args.no_plain:
         out["plain_per_candidate"] = plain_sweep(mgs, torch, attr, imp, kept, k, G, w.bits, s, med["sweep"])
     if args.serve_jobs > 0:
@@ -280,6 +281,47 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, attr_h, imp_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def search_variants(mgs, w, k, G, err, bits, budget_bits):
+    """The paper's two other search devices on the same tables (host only, not
+    in the timed step): the flat exact ILP against the two-step hierarchical
+    solver at the chosen ratio (loss and CPU time, median of 5), and the
+    calibrated reserve-ratio loop with the linear size estimator."""
+    C = w.channels
+    res = mgs.search(w.n, C, k, G, w.bits, err, bits, budget_bits)
+    t = res["best_t"]
+    ng = (int(k[t]) + G - 1) // G
+    e = np.ascontiguousarray(err[t, :, :ng].reshape(C * ng, len(w.bits)))
+    sz = mgs.size_table(np.ascontiguousarray(bits[t, :, :ng].reshape(C * ng, len(w.bits))), mode=0)
+
+    def timed(fn):
+        ts, r = [], None
+        for _ in range(5):
+            t0 = time.perf_counter()
+            r = fn()
+            ts.append(time.perf_counter() - t0)
+        return r, float(np.median(ts)) * 1e3
+    flat, flat_ms = timed(lambda: mgs.ilp_solve(e, sz, budget_bits))
+    hier, hier_ms = timed(lambda: mgs.ilp_hierarchical(e, sz, C, w.bits, budget_bits))
+    cal, cal_ms = timed(lambda: mgs.search_calibrated(w.n, C, k, G, w.bits, err, bits, budget_bits))
+    conv = cal["status"] == mgs.SEARCH_SOLVED
+    out = {"ratio_index": int(t), "budget_bits": int(budget_bits),
+           "flat": {"obj": flat[1], "used": int(flat[2]), "ms": flat_ms},
+           "hierarchical": None if hier is None else {
+               "obj": hier[1], "used": int(hier[2]), "ms": hier_ms, "obj_over_flat": hier[1] / flat[1],
+               "channel_bits": hier[3].tolist()},
+           "calibrated": {"best_t": int(cal["best_t"]), "converged": int(conv.sum()),
+                          "skipped": int((cal["status"] == mgs.SEARCH_SKIPPED).sum()),
+                          "infeasible": int((cal["status"] == mgs.SEARCH_INFEASIBLE).sum()),
+                          "unconverged": int((cal["status"] == mgs.SEARCH_UNCONVERGED).sum()),
+                          "mean_iters_converged": float(cal["iters"][conv].mean()) if conv.any() else None,
+                          "ms": cal_ms}}
+    if cal["best_t"] >= 0:
+        b = cal["best_t"]
+        out["calibrated"]["obj"] = float(cal["obj"][b])
+        out["calibrated"]["actual_over_budget"] = float(cal["actual"][b]) / budget_bits
+    return out
 
 
 def plain_sweep(mgs, torch, attr, imp, kept, k, G, bits, s, batched_ms):

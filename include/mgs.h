@@ -272,6 +272,7 @@ int mgs_graph_destroy(void* graph);
 #define MGS_SEARCH_SKIPPED 1        /* doubled 8-bit size below the budget (or no groups) */
 #define MGS_SEARCH_INFEASIBLE 2     /* even the smallest allocation exceeds the budget */
 #define MGS_SEARCH_PRUNED 3         /* LP lower bound above the best optimum: not solved */
+#define MGS_SEARCH_UNCONVERGED 4    /* calibrated search: max_iter allocations, none within tol */
 
 int mgs_ilp_solve(const double* h_err, const int64_t* h_size, int64_t ncls, int32_t nopt,
                   int64_t budget, uint8_t* h_choice, double* h_obj, int64_t* h_used);
@@ -283,6 +284,50 @@ int mgs_search(const mgs_sweep_desc* desc, const double* h_err, const double* h_
                int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t flags,
                int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
                int32_t* h_status);
+
+/* ======================================================================
+ * mgs_ilp_hierarchical: the paper's two-step solver (section "Solve the
+ * MINLP", paragraph "Hierarchical Solver") for one ILP instance whose
+ * classes are C channels x ng groups, channel-major (the class order of
+ * mgs_search).  Step 1 picks one option per channel, shared by all of its
+ * groups (channel loss and size: the sums over its groups, in group order),
+ * exactly under the whole budget.  Step 2 gives channel c the share
+ * S_c = floor(budget * Q_c / sum_c Q_c), Q_c the bit-width h_bitlist[] of its
+ * step-1 option, and solves each channel's group-level ILP exactly within
+ * S_c.  Writes h_choice[C * ng] (option indices), *h_obj and *h_used (sums
+ * over the channels) and, when not NULL, h_chan_bits[C] (Q_c) and
+ * h_chan_budget[C] (S_c).  The result never exceeds the budget and its loss
+ * is never below the flat optimum of mgs_ilp_solve.  Returns MGS_EINFEASIBLE
+ * when step 1 finds no allocation or a channel's share cannot hold its
+ * cheapest allocation; MGS_EINVAL on bad arguments (as mgs_ilp_solve, plus
+ * a bit-width of 0 in h_bitlist); MGS_ELIMIT as mgs_ilp_solve.
+ *
+ * mgs_search_calibrated: Algorithm 1 "Hyperparameter Optimization" with the
+ * paper's linear size estimator (equation "size_estim": n * b bits per group
+ * plus 72 metadata bits plus the calibration term S_delta) and the entropy
+ * table as the measured size (ceil(bits) + 72 per group).  Per ratio t:
+ * start from all groups at 8 bits (measured size: its entropy size, or
+ * n * 8 + 72 per group when 8 is not listed); skip t when twice that size is
+ * below the budget; then up to max_iter times: S_delta = measured - linear
+ * estimate of the current allocation, solve the exact ILP with linear sizes
+ * under budget - S_delta, measure the new allocation, and stop once
+ * |measured - budget| * 10^6 < tol_ppm * budget (the paper uses 5 %,
+ * tol_ppm = 50000).  Writes per ratio h_obj[t] (loss of the last
+ * allocation, NaN if none), h_actual[t] (its measured size, or the all-8-bit
+ * size), h_iters[t] (ILP solves) and, if not NULL, h_status[t]
+ * (MGS_SEARCH_SOLVED when converged, _SKIPPED, _INFEASIBLE or
+ * _UNCONVERGED); h_best_t and h_best_bits[C][ceil(k_best / G)] name the
+ * converged ratio with the smallest loss (ties: larger k_t).  Returns
+ * MGS_EINFEASIBLE when no ratio converged.
+ * ====================================================================== */
+int mgs_ilp_hierarchical(const double* h_err, const int64_t* h_size, int32_t C, int64_t ng,
+                         int32_t nopt, const uint8_t* h_bitlist, int64_t budget, uint8_t* h_choice,
+                         double* h_obj, int64_t* h_used, uint8_t* h_chan_bits, int64_t* h_chan_budget);
+
+int mgs_search_calibrated(const mgs_sweep_desc* desc, const double* h_err, const double* h_bits,
+                          int64_t budget_bits, int32_t tol_ppm, int32_t max_iter, int32_t threads,
+                          int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_actual,
+                          int32_t* h_iters, int32_t* h_status);
 
 #ifdef __cplusplus
 }

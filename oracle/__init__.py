@@ -202,3 +202,127 @@ def choose_ratio(per_tau):
                 r["obj"] == per_tau[best]["obj"] and r["tau"] > per_tau[best]["tau"]):
             best = i
     return best
+
+
+def ilp_hierarchical(err, size, C: int, bit_list, budget: int, solve=None):
+    """The two-step solver of section "Solve the MINLP", paragraph
+    "Hierarchical Solver": first one bit-width per channel (every group of the
+    channel at that option; the channel's loss and size are the sums over its
+    groups, added in group order), solved exactly under the whole budget
+    S_T; then the channel budgets S_c = floor(S_T * Q_c / sum_c Q_c) and, per
+    channel, the exact group-level ILP within S_c.
+
+    Classes are C channels x ng groups, channel-major.  Returns (choice, obj,
+    used, chan_bits, chan_budget) or None when a step has no feasible
+    allocation.  ``solve`` is the exact solver (default: ``ilp_dp``).
+    """
+    solve = solve or ilp_dp
+    err = np.asarray(err, dtype=np.float64)
+    size = np.asarray(size, dtype=np.int64)
+    ncls, nopt = err.shape
+    ng = ncls // C
+    assert ng * C == ncls
+    ec = np.zeros((C, nopt), dtype=np.float64)
+    sc = np.zeros((C, nopt), dtype=np.int64)
+    for c in range(C):
+        for g in range(ng):
+            for j in range(nopt):
+                ec[c, j] += err[c * ng + g, j]
+                sc[c, j] += size[c * ng + g, j]
+    top = solve(ec, sc, budget)
+    if top is None:
+        return None
+    q = [int(bit_list[j]) for j in top[0]]
+    qsum = sum(q)
+    choice = np.empty(ncls, dtype=np.uint8)
+    obj, used, shares = 0.0, 0, []
+    for c in range(C):
+        share = (int(budget) * q[c]) // qsum
+        r = solve(err[c * ng:(c + 1) * ng], size[c * ng:(c + 1) * ng], share)
+        if r is None:
+            return None
+        choice[c * ng:(c + 1) * ng] = r[0]
+        obj += r[1]
+        used += r[2]
+        shares.append(share)
+    return choice, obj, used, np.array(q, dtype=np.uint8), np.array(shares, dtype=np.int64)
+
+
+SOLVED, SKIPPED, INFEASIBLE, UNCONVERGED = 0, 1, 2, 4
+
+
+def search_calibrated(err_tab, bits_tab, k, G: int, bit_list, budget: int, tol_ppm: int = 50000,
+                      max_iter: int = 16, solve=None):
+    """Algorithm 1 "Hyperparameter Optimization" with the size estimator of
+    equation "size_estim" (linear: n * b bits per group + 72 metadata bits +
+    S_delta) and the entropy table as the measured size (ceil(bits) + 72 per
+    group).
+
+    Per ratio t, in the algorithm's order: start from every group at 8 bits
+    and measure it (n * 8 + 72 per group when 8 is not a candidate); skip the
+    ratio when twice that size is below the budget S_T; then repeat: S_delta =
+    measured size - linear estimate of the current allocation, solve the ILP
+    with linear sizes and the constraint estimate + S_delta <= S_T, measure
+    the new allocation, and stop when |S_a - S_T| / S_T < tol (integer test
+    |S_a - S_T| * 10^6 < tol_ppm * S_T), at most ``max_iter`` solves.  The
+    kept ratio is the converged one with the smallest loss (ties: larger k,
+    then larger index).
+
+    ``err_tab`` / ``bits_tab``: [T][C][Gmax][nb] tables.  Returns dict(best_t,
+    best_bits [C][ng] or None, and per ratio obj, actual, iters, status).
+    """
+    solve = solve or ilp_dp
+    err_tab = np.asarray(err_tab, dtype=np.float64)
+    bits_tab = np.asarray(bits_tab, dtype=np.float64)
+    T, C, _, nb = err_tab.shape
+    bl = [int(b) for b in bit_list]
+    i8 = bl.index(8) if 8 in bl else None
+    obj = np.full(T, np.nan)
+    actual = np.zeros(T, dtype=np.int64)
+    iters = np.zeros(T, dtype=np.int32)
+    status = np.full(T, UNCONVERGED, dtype=np.int32)
+    choices = [None] * T
+    for t in range(T):
+        kt = int(k[t])
+        ng = (kt + G - 1) // G
+        if ng == 0:
+            status[t] = SKIPPED
+            continue
+        e = err_tab[t, :, :ng].reshape(C * ng, nb)
+        b = bits_tab[t, :, :ng].reshape(C * ng, nb)
+        n = np.tile([min(G, kt - g * G) for g in range(ng)], C)
+        act = size_table(b, mode="entropy")
+        lin = size_table(b, n, bl, "linear")
+        sa = sum(int(act[i, i8]) if i8 is not None else int(n[i]) * 8 + METADATA_BITS for i in range(C * ng))
+        est = sum(int(n[i]) * 8 + METADATA_BITS for i in range(C * ng))
+        actual[t] = sa
+        if 2 * sa < budget:
+            status[t] = SKIPPED
+            continue
+        for it in range(1, max_iter + 1):
+            delta = sa - est
+            limit = budget - delta
+            r = solve(e, lin, limit) if limit >= 0 else None
+            if r is None:
+                status[t] = INFEASIBLE
+                break
+            choice, o, used = r
+            sa = sum(int(act[i, choice[i]]) for i in range(C * ng))
+            est = int(used)
+            obj[t], actual[t], iters[t], choices[t] = o, sa, it, choice
+            if abs(sa - budget) * 1000000 < tol_ppm * budget:
+                status[t] = SOLVED
+                break
+    best = None
+    for t in range(T):
+        if status[t] != SOLVED:
+            continue
+        if best is None or obj[t] < obj[best] or (obj[t] == obj[best] and (k[t] > k[best] or (
+                k[t] == k[best] and t > best))):
+            best = t
+    best_bits = None
+    if best is not None:
+        ng = (int(k[best]) + G - 1) // G
+        best_bits = np.array([bl[j] for j in choices[best]], dtype=np.uint8).reshape(C, ng)
+    return {"best_t": -1 if best is None else best, "best_bits": best_bits, "obj": obj, "actual": actual,
+            "iters": iters, "status": status}

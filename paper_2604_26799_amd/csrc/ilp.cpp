@@ -685,6 +685,35 @@ extern "C" int mgs_size_table(const double* h_bits, const int64_t* h_n, int64_t 
     return MGS_OK;
 }
 
+// The ILP instance of ratio t from a sweep's host tables (layout of
+// mgs_quant_sweep): loss and entropy bits per (class, option), classes
+// channel-major then group, and each class's element count.  False if a
+// loss is not finite.
+static bool ratio_instance(const mgs_sweep_desc* d, const double* h_err, const double* h_bits, int t,
+                           int64_t gmaxn, std::vector<double>& E, std::vector<double>& B,
+                           std::vector<int64_t>& n) {
+    const int C = d->C, G = d->G, nb = d->nb;
+    const int64_t k = d->h_k[t];
+    const int64_t ng = (k + G - 1) / G;
+    const int64_t ncls = (int64_t)C * ng;
+    E.resize(ncls * nb);
+    B.resize(ncls * nb);
+    n.resize(ncls);
+    for (int c = 0; c < C; ++c)
+        for (int64_t g = 0; g < ng; ++g) {
+            const int64_t cls = (int64_t)c * ng + g;
+            const int64_t slot = ((int64_t)t * C + c) * gmaxn + g;
+            n[cls] = std::min<int64_t>(G, k - g * G);
+            for (int i = 0; i < nb; ++i) {
+                E[cls * nb + i] = h_err[slot * nb + i];
+                B[cls * nb + i] = h_bits[slot * nb + i];
+            }
+        }
+    for (double v : E)
+        if (!std::isfinite(v)) return false;
+    return true;
+}
+
 extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const double* h_bits,
                           int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t flags,
                           int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
@@ -723,23 +752,13 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
             state[t] = MGS_SEARCH_SKIPPED;
             continue;
         }
-        std::vector<double> bt(ncls * nb);
-        std::vector<int64_t> n(ncls);
-        E[t].resize(ncls * nb);
+        std::vector<double> bt;
+        std::vector<int64_t> n;
         S[t].resize(ncls * nb);
-        for (int c = 0; c < C; ++c)
-            for (int64_t g = 0; g < ng; ++g) {
-                int64_t cls = (int64_t)c * ng + g;
-                int64_t slot = ((int64_t)t * C + c) * gmaxn + g;
-                n[cls] = std::min<int64_t>(G, k - g * G);
-                for (int i = 0; i < nb; ++i) {
-                    E[t][cls * nb + i] = h_err[slot * nb + i];
-                    bt[cls * nb + i] = h_bits[slot * nb + i];
-                }
-            }
-        for (double v : E[t])
-            if (!std::isfinite(v)) st[t] = MGS_EINVAL;
-        if (st[t]) continue;
+        if (!ratio_instance(d, h_err, h_bits, t, gmaxn, E[t], bt, n)) {
+            st[t] = MGS_EINVAL;
+            continue;
+        }
         int rc = mgs_size_table(bt.data(), n.data(), ncls, nb, d->h_bits, size_mode, S[t].data());
         if (rc) {
             st[t] = rc;
@@ -796,6 +815,173 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
     }
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
     for (int i = 0; i < (int)todo.size(); ++i) solve_one(todo[i]);
+    for (int t = 0; t < T; ++t)
+        if (st[t] != MGS_OK) return st[t];
+    if (h_status)
+        for (int t = 0; t < T; ++t) h_status[t] = state[t];
+    int best = -1;
+    for (int t = 0; t < T; ++t) {
+        if (state[t] != MGS_SEARCH_SOLVED) continue;
+        if (best < 0 || h_obj[t] < h_obj[best] ||
+            (h_obj[t] == h_obj[best] &&
+             (d->h_k[t] > d->h_k[best] || (d->h_k[t] == d->h_k[best] && t > best))))
+            best = t;
+    }
+    *h_best_t = best;
+    if (best < 0) return MGS_EINFEASIBLE;
+    const int64_t ng = (d->h_k[best] + G - 1) / G;
+    for (int64_t cls = 0; cls < (int64_t)C * ng; ++cls) h_best_bits[cls] = d->h_bits[choice[best][cls]];
+    return MGS_OK;
+}
+
+// ------------------------------------------------------------- hierarchical solver
+// Paper, section "Hierarchical Solver": first the channel-level bit-widths
+// Q_c (one option per channel, shared by all of its groups), then each
+// channel's budget S_c = S_T * Q_c / sum_c Q_c and, per channel, the
+// group-level ILP within S_c.  Both steps use the exact solver above.
+extern "C" int mgs_ilp_hierarchical(const double* h_err, const int64_t* h_size, int32_t C, int64_t ng,
+                                    int32_t nopt, const uint8_t* h_bitlist, int64_t budget,
+                                    uint8_t* h_choice, double* h_obj, int64_t* h_used,
+                                    uint8_t* h_chan_bits, int64_t* h_chan_budget) {
+    if (C < 1 || ng < 1 || nopt < 1 || nopt > 255 || budget < 0 || !h_err || !h_size || !h_bitlist ||
+        !h_choice || !h_obj || !h_used)
+        return MGS_EINVAL;
+    const int64_t ncls = (int64_t)C * ng;
+    for (int64_t i = 0; i < ncls * nopt; ++i)
+        if (!std::isfinite(h_err[i]) || h_size[i] < 0) return MGS_EINVAL;
+    for (int j = 0; j < nopt; ++j)
+        if (h_bitlist[j] < 1) return MGS_EINVAL;
+    // step 1: a channel's option is every one of its groups at that option;
+    // its loss and size are the sums over the groups (in group order)
+    std::vector<double> ec((size_t)C * nopt, 0.0);
+    std::vector<int64_t> sc((size_t)C * nopt, 0);
+    for (int c = 0; c < C; ++c)
+        for (int64_t g = 0; g < ng; ++g)
+            for (int j = 0; j < nopt; ++j) {
+                ec[(size_t)c * nopt + j] += h_err[((int64_t)c * ng + g) * nopt + j];
+                sc[(size_t)c * nopt + j] += h_size[((int64_t)c * ng + g) * nopt + j];
+            }
+    std::vector<uint8_t> qc((size_t)C);
+    double o = 0.0;
+    int64_t u = 0;
+    int rc = solve(ec.data(), sc.data(), C, nopt, budget, qc.data(), &o, &u);
+    if (rc) return rc;
+    // step 2: the channel shares of the budget, then each channel alone
+    int64_t qsum = 0;
+    for (int c = 0; c < C; ++c) qsum += h_bitlist[qc[c]];
+    double obj = 0.0;
+    int64_t used = 0;
+    for (int c = 0; c < C; ++c) {
+        const int64_t share = (int64_t)((__int128)budget * h_bitlist[qc[c]] / qsum);
+        if (h_chan_bits) h_chan_bits[c] = h_bitlist[qc[c]];
+        if (h_chan_budget) h_chan_budget[c] = share;
+        rc = solve(h_err + (int64_t)c * ng * nopt, h_size + (int64_t)c * ng * nopt, ng, nopt, share,
+                   h_choice + (int64_t)c * ng, &o, &u);
+        if (rc) return rc;  // MGS_EINFEASIBLE: the share cannot hold the channel's cheapest allocation
+        obj += o;
+        used += u;
+    }
+    *h_obj = obj;
+    *h_used = used;
+    return MGS_OK;
+}
+
+// ------------------------------------------------------- calibrated search (Algorithm 1)
+// Paper: Algorithm 1 "Hyperparameter Optimization" with the linear size
+// estimator of equation "size_estim" (n * b bits per group plus its 72
+// metadata bits, plus the calibration term S_delta).  Per ratio: the all-8-bit
+// configuration gives the first measured size S_a; a ratio whose doubled S_a
+// is below the budget is skipped; then repeatedly S_delta = S_a - (linear
+// estimate of the current allocation), the exact ILP with linear sizes under
+// the budget S_T - S_delta gives the next allocation, and its measured size
+// S_a (the entropy table: ceil(bits) + 72 per group) ends the loop once
+// |S_a - S_T| < tol * S_T.  Among converged ratios the smallest loss wins
+// (ties: larger k, then larger index).
+extern "C" int mgs_search_calibrated(const mgs_sweep_desc* d, const double* h_err, const double* h_bits,
+                                     int64_t budget_bits, int32_t tol_ppm, int32_t max_iter,
+                                     int32_t threads, int32_t* h_best_t, uint8_t* h_best_bits,
+                                     double* h_obj, int64_t* h_actual, int32_t* h_iters,
+                                     int32_t* h_status) {
+    if (!d || !d->h_k || !d->h_bits || !h_err || !h_bits || !h_best_t || !h_best_bits || !h_obj ||
+        !h_actual || !h_iters)
+        return MGS_EINVAL;
+    if (d->C < 1 || d->T < 1 || d->T > MGS_MAX_RATIOS || d->G < 1 || d->nb < 1 ||
+        d->nb > MGS_MAX_BITS || budget_bits < 1 || tol_ppm < 0 || tol_ppm > 1000000 || max_iter < 1)
+        return MGS_EINVAL;
+    const int C = d->C, T = d->T, G = d->G, nb = d->nb;
+    int64_t kmax = 0;
+    for (int t = 0; t < T; ++t) {
+        if (d->h_k[t] < 0) return MGS_EINVAL;
+        kmax = std::max(kmax, d->h_k[t]);
+    }
+    const int64_t gmaxn = (kmax + G - 1) / G;
+    int b8 = -1;
+    for (int i = 0; i < nb; ++i)
+        if (d->h_bits[i] == 8) b8 = i;
+    const int nthr = threads > 0 ? threads : omp_get_max_threads();
+    std::vector<int> st(T, MGS_OK), state(T, MGS_SEARCH_UNCONVERGED);
+    std::vector<std::vector<uint8_t>> choice(T);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+    for (int t = 0; t < T; ++t) {
+        h_obj[t] = std::numeric_limits<double>::quiet_NaN();
+        h_actual[t] = 0;
+        h_iters[t] = 0;
+        const int64_t ng = (d->h_k[t] + G - 1) / G;
+        const int64_t ncls = (int64_t)C * ng;
+        if (ncls == 0) {
+            state[t] = MGS_SEARCH_SKIPPED;
+            continue;
+        }
+        std::vector<double> E, B;
+        std::vector<int64_t> n;
+        if (!ratio_instance(d, h_err, h_bits, t, gmaxn, E, B, n)) {
+            st[t] = MGS_EINVAL;
+            continue;
+        }
+        std::vector<int64_t> act(ncls * nb), lin(ncls * nb);
+        int rc = mgs_size_table(B.data(), n.data(), ncls, nb, d->h_bits, 0, act.data());
+        if (!rc) rc = mgs_size_table(B.data(), n.data(), ncls, nb, d->h_bits, 1, lin.data());
+        if (rc) {
+            st[t] = rc;
+            continue;
+        }
+        int64_t sa = 0, est = 0;  // measured and estimated size of the all-8-bit start
+        for (int64_t cls = 0; cls < ncls; ++cls) {
+            sa += (b8 >= 0) ? act[cls * nb + b8] : n[cls] * 8 + kMetaBits;
+            est += n[cls] * 8 + kMetaBits;
+        }
+        h_actual[t] = sa;
+        if (2 * sa < budget_bits) {
+            state[t] = MGS_SEARCH_SKIPPED;
+            continue;
+        }
+        choice[t].resize(ncls);
+        for (int it = 1; it <= max_iter; ++it) {
+            const int64_t delta = sa - est;
+            double o = 0.0;
+            int64_t u = 0;
+            rc = solve(E.data(), lin.data(), ncls, nb, budget_bits - delta, choice[t].data(), &o, &u);
+            if (rc == MGS_EINFEASIBLE) {
+                state[t] = MGS_SEARCH_INFEASIBLE;
+                break;
+            }
+            if (rc) {
+                st[t] = rc;
+                break;
+            }
+            sa = 0;
+            for (int64_t cls = 0; cls < ncls; ++cls) sa += act[cls * nb + choice[t][cls]];
+            est = u;
+            h_obj[t] = o;
+            h_actual[t] = sa;
+            h_iters[t] = it;
+            const int64_t dev = sa > budget_bits ? sa - budget_bits : budget_bits - sa;
+            if (dev * 1000000 < (int64_t)tol_ppm * budget_bits) {
+                state[t] = MGS_SEARCH_SOLVED;
+                break;
+            }
+        }
+    }
     for (int t = 0; t < T; ++t)
         if (st[t] != MGS_OK) return st[t];
     if (h_status)

@@ -65,6 +65,8 @@ SIGNATURES = {
     "mgs_ilp_solve": (ct.c_int, [P, P, I64, I32, I64, P, P, P]),
     "mgs_size_table": (ct.c_int, [P, P, I64, I32, P, I32, P]),
     "mgs_search": (ct.c_int, [P, P, P, I64, I32, I32, I32, P, P, P, P, P]),
+    "mgs_ilp_hierarchical": (ct.c_int, [P, P, I32, I64, I32, P, I64, P, P, P, P, P]),
+    "mgs_search_calibrated": (ct.c_int, [P, P, P, I64, I32, I32, I32, P, P, P, P, P, P]),
 }
 
 
@@ -397,7 +399,7 @@ def size_table(bits_table: np.ndarray, n_per_group=None, bit_list=None, mode: in
 
 
 SEARCH_ALL = 1
-SEARCH_SOLVED, SEARCH_SKIPPED, SEARCH_INFEASIBLE, SEARCH_PRUNED = 0, 1, 2, 3
+SEARCH_SOLVED, SEARCH_SKIPPED, SEARCH_INFEASIBLE, SEARCH_PRUNED, SEARCH_UNCONVERGED = 0, 1, 2, 3, 4
 
 
 def search(N: int, C: int, k, G: int, bits, err: np.ndarray, bits_table: np.ndarray, budget_bits: int,
@@ -428,3 +430,59 @@ def search(N: int, C: int, k, G: int, bits, err: np.ndarray, bits_table: np.ndar
     ng = (int(kk[t]) + G - 1) // G if t >= 0 else 0
     return {"best_t": t, "best_bits": best_bits[:C * ng].reshape(C, ng) if t >= 0 else None,
             "obj": obj, "used": used, "status": status}
+
+
+def ilp_hierarchical(err: np.ndarray, size: np.ndarray, C: int, bit_list, budget: int):
+    """Two-step (channel, then group) 0-1 ILP over classes C x ng, channel-major.
+
+    Returns (choice u8[C*ng], obj, used, chan_bits u8[C], chan_budget i64[C]), or None
+    when a step is infeasible.
+    """
+    err = np.ascontiguousarray(err, dtype=np.float64)
+    size = np.ascontiguousarray(size, dtype=np.int64)
+    ncls, nopt = err.shape
+    assert ncls % C == 0, "classes must be C channels x ng groups"
+    bl = np.ascontiguousarray(bit_list, dtype=np.uint8)
+    assert bl.size == nopt
+    choice = np.empty(ncls, dtype=np.uint8)
+    chan_bits = np.empty(C, dtype=np.uint8)
+    chan_budget = np.empty(C, dtype=np.int64)
+    obj = ct.c_double(0.0)
+    used = ct.c_int64(0)
+    code = lib().mgs_ilp_hierarchical(_np_ptr(err), _np_ptr(size), C, ncls // C, nopt, _np_ptr(bl),
+                                      int(budget), _np_ptr(choice), ct.byref(obj), ct.byref(used),
+                                      _np_ptr(chan_bits), _np_ptr(chan_budget))
+    if code == EINFEASIBLE:
+        return None
+    _check(code, "mgs_ilp_hierarchical")
+    return choice, obj.value, used.value, chan_bits, chan_budget
+
+
+def search_calibrated(N: int, C: int, k, G: int, bits, err: np.ndarray, bits_table: np.ndarray,
+                      budget_bits: int, tol_ppm: int = 50000, max_iter: int = 16, threads: int = 0):
+    """The calibrated reserve-ratio search (linear size estimator + measured entropy size).
+
+    Returns dict(best_t, best_bits u8[C][ng], obj f64[T], actual i64[T], iters i32[T],
+    status i32[T]); best_t is -1 when no ratio converged.
+    """
+    d = sweep_desc(N, C, k, G, bits)
+    err = np.ascontiguousarray(err, dtype=np.float64)
+    bt = np.ascontiguousarray(bits_table, dtype=np.float64)
+    T = d.T
+    kk = d._keep[0]
+    ngmax = (int(kk.max()) + G - 1) // G
+    best_t = ct.c_int32(-1)
+    best_bits = np.zeros(C * max(ngmax, 1), dtype=np.uint8)
+    obj = np.empty(T, dtype=np.float64)
+    actual = np.empty(T, dtype=np.int64)
+    iters = np.empty(T, dtype=np.int32)
+    status = np.empty(T, dtype=np.int32)
+    code = lib().mgs_search_calibrated(ct.byref(d), _np_ptr(err), _np_ptr(bt), int(budget_bits), int(tol_ppm),
+                                       int(max_iter), threads, ct.byref(best_t), _np_ptr(best_bits),
+                                       _np_ptr(obj), _np_ptr(actual), _np_ptr(iters), _np_ptr(status))
+    if code not in (OK, EINFEASIBLE):
+        _check(code, "mgs_search_calibrated")
+    t = best_t.value
+    ng = (int(kk[t]) + G - 1) // G if t >= 0 else 0
+    return {"best_t": t, "best_bits": best_bits[:C * ng].reshape(C, ng) if t >= 0 else None,
+            "obj": obj, "actual": actual, "iters": iters, "status": status}

@@ -86,6 +86,40 @@ def test_multi_sweep_rejects_bad_job_lists():
     assert L.mgs_quant_sweep_multi_ws_bytes(jobs, 2) > L.mgs_quant_sweep_multi_ws_bytes(jobs, 1) > 0
 
 
+def test_host_solvers_reject_bad_arguments():
+    L = mgs.lib()
+    P = lambda a: a.ctypes.data_as(ct.c_void_p)
+    err = np.zeros((4, 2))
+    size = np.full((4, 2), 5, np.int64)
+    ch = np.zeros(4, np.uint8)
+    o, u = ct.c_double(), ct.c_int64()
+    bl = np.array([2, 4], np.uint8)
+
+    def hier(*, e=err, C=2, ng=2, nopt=2, bits=bl, budget=100):
+        return L.mgs_ilp_hierarchical(P(e) if e is not None else None, P(size), C, ng, nopt, P(bits), budget,
+                                      P(ch), ct.byref(o), ct.byref(u), None, None)
+    assert hier() == mgs.OK
+    assert hier(bits=np.array([0, 4], np.uint8)) == mgs.EINVAL  # bit-width 0
+    assert hier(C=0) == mgs.EINVAL
+    assert hier(budget=-1) == mgs.EINVAL
+    assert hier(e=None) == mgs.EINVAL
+    assert hier(e=np.full((4, 2), np.nan)) == mgs.EINVAL
+    assert hier(budget=5) == mgs.EINFEASIBLE
+    d = mgs.sweep_desc(20, 1, [20], 10, [4, 8])
+    tab = np.zeros((1, 1, 2, 2))
+    bt, ob = ct.c_int32(), np.zeros(2, np.uint8)
+    outs = [np.zeros(1), np.zeros(1, np.int64), np.zeros(1, np.int32), np.zeros(1, np.int32)]
+
+    def calib(budget=100, tol=50000, iters=4):
+        return L.mgs_search_calibrated(ct.byref(d), P(tab), P(tab), budget, tol, iters, 1, ct.byref(bt), P(ob),
+                                       *[P(x) for x in outs])
+    assert calib() in (mgs.OK, mgs.EINFEASIBLE)
+    assert calib(budget=0) == mgs.EINVAL
+    assert calib(tol=-1) == mgs.EINVAL
+    assert calib(tol=1000001) == mgs.EINVAL
+    assert calib(iters=0) == mgs.EINVAL
+
+
 def test_graph_calls_reject_null_handles():
     L = mgs.lib()
     h = ct.c_void_p()

@@ -145,3 +145,57 @@ def test_search_vs_oracle(orc):
         assert res["best_t"] == best
         want = np.asarray(w.bits, np.uint8)[rows[best]["sol"][0]].reshape(w.channels, -1)
         assert np.array_equal(res["best_bits"], want)
+
+
+@pytest.mark.parametrize("kind", ["mono", "ties", "free"])
+def test_hierarchical_vs_oracle(orc, kind):
+    """The library's two-step solver against the oracle's (channel level under
+    the whole budget, shares floor(S_T Q_c / sum Q_c), per-channel ILPs)."""
+    rng = np.random.default_rng({"mono": 11, "ties": 12, "free": 13}[kind])
+    for _ in range(40):
+        C, ng, nopt = int(rng.integers(1, 6)), int(rng.integers(1, 6)), int(rng.integers(1, 6))
+        bl = sorted(rng.choice(np.arange(1, 17), nopt, replace=False).tolist())
+        err, size = rand_table(rng, C * ng, nopt, kind)
+        budget = int(rng.integers(0, int(size.max(axis=1).sum()) + 2))
+        want = orc.ilp_hierarchical(err, size, C, bl, budget)
+        got = mgs.ilp_hierarchical(err, size, C, bl, budget)
+        if want is None:
+            assert got is None
+            continue
+        assert got is not None
+        assert got[0].tolist() == want[0].tolist()
+        assert got[1] == pytest.approx(want[1], rel=1e-12, abs=1e-12)
+        assert got[2] == want[2]
+        assert got[3].tolist() == want[3].tolist() and got[4].tolist() == want[4].tolist()
+        flat = mgs.ilp_solve(err, size, budget)
+        assert flat is not None and got[1] >= flat[1] - 1e-9 and got[2] <= budget
+
+
+def test_calibrated_search_vs_oracle(orc):
+    """Algorithm 1 with the linear estimator and measured entropy sizes, on the
+    oracle's tables of a small scene, for budgets that converge, oscillate and
+    skip ratios; with 8 among the candidates and without."""
+    for bits in ([2, 4, 6, 8], [3, 5, 7]):
+        w = synth.SweepWorkload("t", 5000, 11, synth.ratios_uniform(synth.Fraction(2, 10), synth.Fraction(9, 10), 4),
+                                512, bits)
+        attr, imp = w.make()
+        attr = np.ascontiguousarray(attr[:5])  # five channels keep the oracle's DP small
+        w.channels = 5
+        k = w.k
+        kept = orc.prune_select(imp, k)
+        tab = orc.quant_sweep(attr, imp, kept, k, w.group, w.bits)
+        raw_bits = w.n * w.channels * 32
+        for ratio in (6, 9, 14, 25, 60):
+            budget = raw_bits // ratio
+            for tol in (50000, 5000):
+                want = orc.search_calibrated(tab["err"], tab["bits"], k, w.group, w.bits, budget, tol_ppm=tol,
+                                             max_iter=6)
+                got = mgs.search_calibrated(w.n, w.channels, k, w.group, w.bits, tab["err"], tab["bits"], budget,
+                                            tol_ppm=tol, max_iter=6)
+                assert got["status"].tolist() == want["status"].tolist(), (bits, ratio, tol)
+                assert got["iters"].tolist() == want["iters"].tolist()
+                assert got["actual"].tolist() == want["actual"].tolist()
+                np.testing.assert_allclose(got["obj"], want["obj"], rtol=1e-12, equal_nan=True)
+                assert got["best_t"] == want["best_t"]
+                if want["best_t"] >= 0:
+                    assert np.array_equal(got["best_bits"], want["best_bits"])

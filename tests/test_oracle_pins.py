@@ -355,3 +355,102 @@ def test_choose_ratio_rule(orc):
         {"tau": Fraction(5, 10), "size8": 99, "budget": 100, "obj": 7.0},
     ]
     assert orc.choose_ratio(rows) == 3
+
+
+# --------------------------------------------------------------- hierarchical solver
+# Two channels x two groups of n = 10 elements, candidate bit-widths {2, 4};
+# sizes are the linear n * b + 72 (92 and 112 bits).  Channel-level options:
+# channel 0 at b = 2 costs loss 18 / 184 bits, at b = 4 loss 3 / 224 bits;
+# channel 1 at b = 2 loss 7 / 184 bits, at b = 4 loss 5.5 / 224 bits.
+HIER_ERR = np.array([[10.0, 1.0], [8.0, 2.0], [3.0, 2.5], [4.0, 3.0]])
+HIER_SIZE = np.array([[92, 112]] * 4, dtype=np.int64)
+
+
+def test_hierarchical_budget_split_by_hand(orc):
+    # S_T = 400: only (2, 2) fits at the channel level (368 bits), so both
+    # channels get 400 * 2 / 4 = 200 bits and keep b = 2 in every group
+    choice, obj, used, qc, shares = orc.ilp_hierarchical(HIER_ERR, HIER_SIZE, 2, [2, 4], 400)
+    assert choice.tolist() == [0, 0, 0, 0] and obj == 25.0 and used == 368
+    assert qc.tolist() == [2, 2] and shares.tolist() == [200, 200]
+    # the flat ILP spends the spare 32 bits on the best single upgrade (loss 16)
+    flat = orc.ilp_exhaustive(HIER_ERR, HIER_SIZE, 400)
+    assert flat[0].tolist() == [1, 0, 0, 0] and flat[1] == 16.0
+    # S_T = 500: (4, 4) fits (448 bits), shares 250 each, every group at b = 4,
+    # which is also the flat optimum
+    choice, obj, used, qc, shares = orc.ilp_hierarchical(HIER_ERR, HIER_SIZE, 2, [2, 4], 500)
+    assert choice.tolist() == [1, 1, 1, 1] and obj == 8.5 and used == 448 and shares.tolist() == [250, 250]
+    assert orc.ilp_exhaustive(HIER_ERR, HIER_SIZE, 500)[1] == 8.5
+    # S_T = 420: the channel level picks (4, 2) (loss 10, 408 bits); channel 1's
+    # share 420 * 2 / 6 = 140 bits cannot hold its cheapest 184 bits
+    assert orc.ilp_hierarchical(HIER_ERR, HIER_SIZE, 2, [2, 4], 420) is None
+
+
+def test_hierarchical_never_beats_flat(orc):
+    """Brute force on tiny random instances: the two-step result fits the
+    budget, each channel's part is optimal for its share, and its loss is never
+    below the flat optimum."""
+    rng = np.random.default_rng(5)
+    for _ in range(60):
+        C, ng, nopt = int(rng.integers(1, 4)), int(rng.integers(1, 3)), int(rng.integers(1, 4))
+        bl = sorted(rng.choice(np.arange(1, 17), nopt, replace=False).tolist())
+        err = rng.random((C * ng, nopt)) * 10
+        size = rng.integers(1, 30, (C * ng, nopt))
+        budget = int(rng.integers(0, 40 * C * ng))
+        r = orc.ilp_hierarchical(err, size, C, bl, budget, solve=orc.ilp_exhaustive)
+        flat = orc.ilp_exhaustive(err, size, budget)
+        if r is None:
+            continue
+        choice, obj, used, qc, shares = r
+        assert used <= budget and flat is not None and obj >= flat[1] - 1e-12
+        assert shares.sum() <= budget
+        for c in range(C):
+            sl = slice(c * ng, (c + 1) * ng)
+            part = orc.ilp_exhaustive(err[sl], size[sl], int(shares[c]))
+            assert part is not None and part[0].tolist() == choice[sl].tolist()
+
+
+# ------------------------------------------------------------ calibrated search
+def calib_tables(bits_b4, bits_b8, err_b4=5.0, err_b8=1.0):
+    """One ratio, one channel, two groups of G = 10 elements, b in {4, 8}:
+    linear sizes 112 / 152 bits, measured ceil(bits) + 72."""
+    err = np.array([[[[err_b4, err_b8]] * 2]], dtype=np.float64)     # [T=1][C=1][2][2]
+    bits = np.array([[[[bits_b4, bits_b8]] * 2]], dtype=np.float64)
+    return err, bits
+
+
+def test_calibrated_search_converges_by_hand(orc):
+    # all-8 start measures 2 * 122 = 244 bits against the estimate 304, so
+    # S_delta = -60 and the first ILP may use 310 linear bits: every group at
+    # b = 8 (304), measured 244, within 5 % of S_T = 250
+    err, bits = calib_tables(30.0, 50.0)
+    r = orc.search_calibrated(err, bits, [20], 10, [4, 8], 250)
+    assert r["status"].tolist() == [orc.SOLVED] and r["iters"].tolist() == [1]
+    assert r["obj"][0] == 2.0 and r["actual"].tolist() == [244]
+    assert r["best_t"] == 0 and r["best_bits"].tolist() == [[8, 8]]
+    # doubling the all-8 size (488) stays below S_T = 1000: the ratio is skipped
+    r = orc.search_calibrated(err, bits, [20], 10, [4, 8], 1000)
+    assert r["status"].tolist() == [orc.SKIPPED] and r["iters"].tolist() == [0] and r["best_t"] == -1
+
+
+def test_calibrated_search_oscillates_by_hand(orc):
+    # measured sizes 80 (b = 4) and 150 (b = 8) per group, S_T = 240: all-8
+    # measures 300 (estimate 304) -> S_delta = -4 -> limit 244 -> all b = 4
+    # (224 linear bits), measured 160 -> S_delta = -64 -> limit 304 -> all
+    # b = 8, measured 300 -> ... neither is within 5 %
+    err, bits = calib_tables(8.0, 78.0)
+    r = orc.search_calibrated(err, bits, [20], 10, [4, 8], 240, max_iter=5)
+    assert r["status"].tolist() == [orc.UNCONVERGED] and r["iters"].tolist() == [5]
+    assert r["obj"][0] == 10.0 and r["actual"].tolist() == [160] and r["best_t"] == -1
+    r = orc.search_calibrated(err, bits, [20], 10, [4, 8], 240, max_iter=4)
+    assert r["obj"][0] == 2.0 and r["actual"].tolist() == [300]
+
+
+def test_calibrated_search_ratio_choice(orc):
+    """Two converged ratios: the smaller loss wins; equal losses go to the larger k."""
+    err, bits = calib_tables(30.0, 50.0)
+    e2 = np.concatenate([err, err * 0.5], axis=0)
+    b2 = np.concatenate([bits, bits], axis=0)
+    r = orc.search_calibrated(e2, b2, [20, 20], 10, [4, 8], 250)
+    assert r["best_t"] == 1 and r["obj"].tolist() == [2.0, 1.0]
+    r = orc.search_calibrated(np.concatenate([err, err], axis=0), b2, [20, 20], 10, [4, 8], 250)
+    assert r["best_t"] == 1  # tie, equal k: the later ratio
