@@ -64,32 +64,46 @@ struct VqArgs {
 
 // Prepared codebook and the codeword-norm maximum (the status word, the
 // maximum and the fallback counter are cleared before this kernel).
-__global__ void vq_prep_kernel(VqArgs a) {
+__global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.Kpad) return;
-    __bf16* row = a.cbp + (int64_t)j * a.KP;
-    if (j >= a.K) {
-        for (int k = 0; k < a.KP; ++k) row[k] = (__bf16)0.0f;
-        row[a.D] = (__bf16)1.0e30f;  // padding codewords score ~1e30 and are skipped
-        return;
+    float nrm = 0.0f;  // FP32 bits of non-negative floats order as unsigned ints
+    if (j < a.Kpad) {
+        __bf16* row = a.cbp + (int64_t)j * a.KP;
+        if (j >= a.K) {
+            for (int k = 0; k < a.KP; ++k) row[k] = (__bf16)0.0f;
+            row[a.D] = (__bf16)1.0e30f;  // padding codewords score ~1e30 and are skipped
+        } else {
+            const float* c = a.cb + (int64_t)j * a.D;
+            double n2 = 0.0;
+            bool bad = false;
+            for (int k = 0; k < a.D; ++k) {
+                float v = c[k];
+                bad |= !finite_f32(v);
+                n2 += (double)v * (double)v;
+                row[k] = (__bf16)(-2.0f * v);
+            }
+            float hi = (float)(__bf16)(float)n2;
+            float lo = (float)(n2 - (double)hi);
+            row[a.D] = (__bf16)hi;
+            row[a.D + 1] = (__bf16)lo;
+            for (int k = a.D + 2; k < a.KP; ++k) row[k] = (__bf16)0.0f;
+            if (bad) atomicOr(&a.status->nonfinite, 1u);
+            nrm = (float)sqrt(n2) * (1.0f + 1.0e-6f);
+        }
     }
-    const float* c = a.cb + (int64_t)j * a.D;
-    double n2 = 0.0;
-    bool bad = false;
-    for (int k = 0; k < a.D; ++k) {
-        float v = c[k];
-        bad |= !finite_f32(v);
-        n2 += (double)v * (double)v;
-        row[k] = (__bf16)(-2.0f * v);
+    // the block's largest norm, then one atomic per block (thousands of
+    // atomics on one address serialise)
+    __shared__ uint32_t red[256 / MGS_WAVE];
+    uint32_t m = __float_as_uint(nrm);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, MGS_WAVE));
+    if ((threadIdx.x & (MGS_WAVE - 1)) == 0) red[threadIdx.x / MGS_WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / MGS_WAVE); ++w) m = max(m, red[w]);
+        m = max(m, red[0]);
+        atomicMax(a.cmax_bits, m);
     }
-    float hi = (float)(__bf16)(float)n2;
-    float lo = (float)(n2 - (double)hi);
-    row[a.D] = (__bf16)hi;
-    row[a.D + 1] = (__bf16)lo;
-    for (int k = a.D + 2; k < a.KP; ++k) row[k] = (__bf16)0.0f;
-    if (bad) atomicOr(&a.status->nonfinite, 1u);
-    float nrm = (float)sqrt(n2) * (1.0f + 1.0e-6f);
-    atomicMax(a.cmax_bits, __float_as_uint(nrm));  // non-negative floats order as uints
 }
 
 __device__ __forceinline__ double exact_dist(const float* __restrict__ x, const float* __restrict__ c,
