@@ -19,6 +19,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
@@ -37,7 +38,7 @@ MFMA_BF16_PEAK = 2.5e15       # dense bf16 FLOP/s
 OPS_PER_EVAL = 12             # arithmetic of one evaluation by its definition
 SWEEP_SOURCES = ("paper_2604_26799_amd/csrc/sweep.hip", "paper_2604_26799_amd/csrc/sweep.h",
                  "paper_2604_26799_amd/csrc/common.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_medium_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def parse():
@@ -70,21 +71,27 @@ def sources_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(workload: str):
-    """HBM bytes per sweep launch from the committed counter summary, if it
-    was taken on these kernel sources and this workload."""
-    try:
-        kv = {}
-        with open(TRAFFIC_FILE) as f:
-            for line in f:
-                if ":" in line and not line.startswith("#"):
-                    key, val = line.split(":", 1)
-                    kv[key.strip()] = val.strip()
-        if kv.get("sources") != sources_digest() or kv.get("workload") != workload:
-            return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+def committed_traffic(workload: str, shape):
+    """HBM bytes per sweep launch from a committed counter summary
+    (profiles/sweep_<workload>_traffic*.txt) taken on these kernel sources,
+    this workload and this launch shape; None if there is none."""
+    if shape is None:
         return None
+    want = ",".join(str(v) for v in shape)
+    digest = sources_digest()
+    for path in sorted(glob.glob(os.path.join(PROFILES, f"sweep_{workload}_traffic*.txt"))):
+        try:
+            kv = {}
+            with open(path) as f:
+                for line in f:
+                    if ":" in line and not line.startswith("#"):
+                        key, val = line.split(":", 1)
+                        kv[key.strip()] = val.strip()
+            if kv.get("sources") == digest and kv.get("workload") == workload and kv.get("shape") == want:
+                return float(kv["traffic_bytes_per_launch"])
+        except (OSError, KeyError, ValueError):
+            continue
+    return None
 
 
 def main():
@@ -234,7 +241,7 @@ def main():
     alg_bytes = int(k.sum()) * (4 * C + 8)
     vq_flops = 2.0 * args.vq_n * args.vq_k * 36
     achieved = OPS_PER_EVAL * evals / sweep_avg_s
-    traffic = committed_traffic(w.name)
+    traffic = committed_traffic(w.name, tuned)
     out = {
         "metric": "sweep Gaussian·channel·bitwidth evals/s, %HBM peak; p50/p99 job latency",
         "value": evals * args.steps / elapsed,
