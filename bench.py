@@ -279,6 +279,7 @@ def main():
                "fallback_rows": int(nfb.item())},
     }
     out["search_variants"] = search_variants(mgs, w, k, G, err_h.numpy(), bits_h.numpy(), budget_bits)
+    out["kmeans"] = kmeans_iterations(mgs, torch, sh, cb, s)
     if not args.no_plain:
         out["plain_per_candidate"] = plain_sweep(mgs, torch, attr, imp, kept, k, G, w.bits, s, med["sweep"])
     if args.serve_jobs > 0:
@@ -329,6 +330,29 @@ def search_variants(mgs, w, k, G, err, bits, budget_bits):
         out["calibrated"]["obj"] = float(cal["obj"][b])
         out["calibrated"]["actual_over_budget"] = float(cal["actual"][b]) / budget_bits
     return out
+
+
+def kmeans_iterations(mgs, torch, x, cb, s, batch_rows: int = 1 << 18, iters: int = 5):
+    """Mini-batch k-means iterations around the assignment (seeded batches of
+    the benchmark's SH vectors, a copy of its codebook), HIP events on the
+    stream; not part of the timed step."""
+    N, D = x.shape
+    K = cb.shape[0]
+    cbk = cb.clone()
+    counts = torch.zeros(K, dtype=torch.int64, device=x.device)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    batches = [torch.randint(0, N, (batch_rows,), generator=g).to(x.device) for _ in range(iters + 1)]
+    ws = mgs.workspace(mgs.lib().mgs_kmeans_step_ws_bytes(batch_rows, D, K), x.device)
+    mgs.kmeans_step(x, cbk, counts, batches[0], ws=ws, stream=s)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for i in range(iters):
+        mgs.kmeans_step(x, cbk, counts, batches[i + 1], ws=ws, stream=s, check=False)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    return {"batch_rows": batch_rows, "K": K, "D": D, "ms_per_iteration": ms,
+            "rows_per_s": batch_rows / (ms * 1e-3)}
 
 
 def plain_sweep(mgs, torch, attr, imp, kept, k, G, bits, s, batched_ms):

@@ -217,6 +217,51 @@ int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float* d_cb, int
                   size_t ws_bytes, void* stream);
 
 /* ======================================================================
+ * One mini-batch k-means iteration around the assignment above (paper:
+ * section "Attribute Transformation", paragraph "Clustering 1+D SH
+ * Coefficients": the codebook is refined by a batched clustering strategy,
+ * Sculley's web-scale k-means, over several iterations).
+ *
+ * The batch is the rows d_batch[B] (int64 row indices into d_x[N][D],
+ * chosen by the caller, repeats allowed).  Every batch row is assigned to its
+ * nearest center of d_cb[K][D] by the rule of mgs_vq_assign (written to
+ * d_assign[B] if not NULL); then every center j that received n_j > 0 rows,
+ * having absorbed v_j = d_counts[j] samples before, becomes the running mean
+ *   c_j <- (v_j c_j + sum of its batch rows) / (v_j + n_j)   (FP64, stored FP32)
+ * and d_counts[j] += n_j.  Sculley's per-sample update (eta = 1 / v) reaches
+ * the same mean.  d_cb and d_counts are updated in place (centers with no
+ * rows keep their value).  The FP64 sums are atomic, so the mean is
+ * reproducible to about B * 2^-53 relative before the FP32 rounding.
+ * Workspace: mgs_kmeans_step_ws_bytes(B, D, K).  Errors: MGS_EINVAL
+ * (N < 0, B outside [0, 2^31), D outside [1, MGS_MAX_VQ_DIM], K < 1, NULL
+ * pointers), MGS_EWORKSPACE; non-finite rows or centers, and batch indices
+ * outside [0, N) (gathered as zero rows), raise MGS_ENONFINITE in the
+ * status word.
+ * ====================================================================== */
+size_t mgs_kmeans_step_ws_bytes(int64_t B, int32_t D, int32_t K);
+int mgs_kmeans_step(const float* d_x, int64_t N, int32_t D, const int64_t* d_batch, int64_t B,
+                    float* d_cb, int32_t K, int64_t* d_counts, int32_t* d_assign, void* d_ws,
+                    size_t ws_bytes, void* stream);
+
+/*
+ * Budget-first retention of SH vectors (paper: same paragraph -- the budget
+ * left after the essential components keeps the original vectors of the
+ * top-ranked Gaussians by importance, appended to the codebook and coded
+ * with it).  mgs_vq_retain_count: r = min(N, floor(remaining_bits / (32 D)))
+ * vectors fit (each is stored as D FP32 values like the codebook; 0 when
+ * nothing remains).  mgs_vq_retain: d_top[r] are the retained Gaussians in
+ * ascending index (mgs_prune_select with the single count r); their rows of
+ * d_x[N][D] are copied to rows K .. K+r-1 of d_cb_ext (whose first K rows are
+ * the caller's codebook) and d_idx[d_top[e]] = K + e.  The workspace needs
+ * only the status word (256 bytes); an index outside [0, N) is skipped and
+ * raises MGS_ENONFINITE in it.  Errors: MGS_EINVAL (r outside [0, N], K < 0,
+ * K + r >= 2^31, D outside [1, MGS_MAX_VQ_DIM], NULL pointers), MGS_EWORKSPACE.
+ */
+int64_t mgs_vq_retain_count(int64_t remaining_bits, int64_t N, int32_t D);
+int mgs_vq_retain(const float* d_x, int64_t N, int32_t D, const int32_t* d_top, int64_t r,
+                  float* d_cb_ext, int32_t K, int32_t* d_idx, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ======================================================================
  * Replayable launch sequences (hipGraph).
  *
  * mgs_graph_begin starts capturing `stream` (which must not be the legacy

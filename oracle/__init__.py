@@ -326,3 +326,49 @@ def search_calibrated(err_tab, bits_tab, k, G: int, bit_list, budget: int, tol_p
         best_bits = np.array([bl[j] for j in choices[best]], dtype=np.uint8).reshape(C, ng)
     return {"best_t": -1 if best is None else best, "best_bits": best_bits, "obj": obj, "actual": actual,
             "iters": iters, "status": status}
+
+
+def kmeans_step(x, cb, counts, batch):
+    """One iteration of the batched clustering the paper uses for the
+    higher-degree SH vectors (section "Attribute Transformation", paragraph
+    "Clustering 1+D SH Coefficients", citing Sculley's web-scale k-means):
+    the batch rows are first all assigned to their nearest center (the exact
+    FP64 rule of ``vq_assign``, against the centers before this iteration),
+    then taken in batch order, each moving its center with the per-center
+    learning rate 1 / v:  v_j += 1,  c_j <- (1 - 1/v_j) c_j + (1/v_j) x  (FP64).
+    The updated centers are stored as FP32.  Returns (centers f32 [K][D],
+    counts i64 [K], assignment i32 [B]).
+    """
+    x = np.asarray(x, dtype=np.float32)
+    cb = np.asarray(cb, dtype=np.float32)
+    batch = np.asarray(batch, dtype=np.int64)
+    rows = x[batch]
+    assign, _ = vq_assign(np.ascontiguousarray(rows), cb)
+    c = cb.astype(np.float64)
+    v = np.array(counts, dtype=np.int64).copy()
+    for r in range(batch.size):
+        j = int(assign[r])
+        v[j] += 1
+        eta = 1.0 / float(v[j])
+        c[j] = (1.0 - eta) * c[j] + eta * rows[r].astype(np.float64)
+    return c.astype(np.float32), v, assign
+
+
+def vq_retain(x, imp, cb, idx, remaining_bits: int):
+    """Budget-first retention (same paragraph of the paper): with the bits
+    left after the essential components, keep the original vectors of the
+    most important Gaussians -- r = min(N, floor(remaining / (32 D))) of
+    them, D FP32 values each -- append them to the codebook in ascending
+    Gaussian index and point their index entries at them.  Returns (extended
+    codebook, new index table, r)."""
+    x = np.asarray(x, dtype=np.float32)
+    N, D = x.shape
+    r = 0 if remaining_bits <= 0 else min(N, int(remaining_bits) // (32 * D))
+    idx = np.array(idx, dtype=np.int32).copy()
+    if r == 0:
+        return np.asarray(cb, dtype=np.float32).copy(), idx, 0
+    top = prune_select(np.asarray(imp, dtype=np.float32), [r])
+    K = cb.shape[0]
+    ext = np.concatenate([np.asarray(cb, dtype=np.float32), x[top]], axis=0)
+    idx[top] = K + np.arange(r, dtype=np.int32)
+    return ext, idx, r

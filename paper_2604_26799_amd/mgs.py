@@ -58,6 +58,10 @@ SIGNATURES = {
     "mgs_dequantize": (ct.c_int, [P, I64, I32, I32, P, P, P, P, P]),
     "mgs_vq_assign_ws_bytes": (SZ, [I64, I32, I32]),
     "mgs_vq_assign": (ct.c_int, [P, I64, I32, P, I32, P, P, P, P, SZ, P]),
+    "mgs_kmeans_step_ws_bytes": (SZ, [I64, I32, I32]),
+    "mgs_kmeans_step": (ct.c_int, [P, I64, I32, P, I64, P, I32, P, P, P, SZ, P]),
+    "mgs_vq_retain_count": (I64, [I64, I64, I32]),
+    "mgs_vq_retain": (ct.c_int, [P, I64, I32, P, I64, P, I32, P, P, SZ, P]),
     "mgs_graph_begin": (ct.c_int, [P]),
     "mgs_graph_end": (ct.c_int, [P, ct.POINTER(ct.c_void_p)]),
     "mgs_graph_launch": (ct.c_int, [P, P]),
@@ -368,6 +372,46 @@ def vq_assign(x, cb, want_dist: bool = True, ws=None, stream=None, check: bool =
                                ws.numel(), _stream(stream)), "mgs_vq_assign")
     _finish(ws, check, "mgs_vq_assign", stream)
     return idx, dist, nfb
+
+
+def kmeans_step(x, cb, counts, batch, ws=None, stream=None, check: bool = True):
+    """One mini-batch k-means iteration on the rows ``batch`` (int64) of ``x``:
+    ``cb`` (f32 [K][D]) and ``counts`` (i64 [K]) are updated in place; returns the
+    batch's assignment ``i32[B]``."""
+    torch = _torch()
+    N, D = x.shape
+    K = cb.shape[0]
+    B = batch.numel()
+    dev = x.device
+    need = lib().mgs_kmeans_step_ws_bytes(B, D, K)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    assign = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    _check(lib().mgs_kmeans_step(_dptr(x), N, D, _dptr(batch) if B else None, B, _dptr(cb), K, _dptr(counts),
+                                 _dptr(assign), _dptr(ws), ws.numel(), _stream(stream)), "mgs_kmeans_step")
+    _finish(ws, check, "mgs_kmeans_step", stream)
+    return assign[:B]
+
+
+def vq_retain(x, imp, cb, idx, remaining_bits: int, ws=None, stream=None, check: bool = True):
+    """Budget-first retention: the top-r Gaussians by importance (r from the
+    remaining bits) keep their own vectors.  Returns (extended codebook
+    f32 [K + r][D], r); ``idx`` (i32 [N]) is updated in place."""
+    torch = _torch()
+    N, D = x.shape
+    K = cb.shape[0]
+    r = int(lib().mgs_vq_retain_count(int(remaining_bits), N, D))
+    cb_ext = torch.empty((K + r, D), dtype=torch.float32, device=x.device)
+    cb_ext[:K].copy_(cb)
+    if r == 0:
+        return cb_ext, 0
+    top = prune_select(imp, [r], stream=stream, check=check)
+    if ws is None:
+        ws = workspace(256, x.device)
+    _check(lib().mgs_vq_retain(_dptr(x), N, D, _dptr(top), r, _dptr(cb_ext), K, _dptr(idx), _dptr(ws),
+                               ws.numel(), _stream(stream)), "mgs_vq_retain")
+    _finish(ws, check, "mgs_vq_retain", stream)
+    return cb_ext, r
 
 
 # ----------------------------------------------------------------- host side

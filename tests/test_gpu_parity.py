@@ -443,3 +443,51 @@ def test_vq_workload_sampled(torch, orc):
     np.testing.assert_array_equal(gd[rows], want_d)
     assert (gi >= 0).all() and (gi < 4096).all()
     assert int(host(nfb)[0]) < x.shape[0] // 1000  # exact full scans stay rare
+
+
+def test_kmeans_steps(torch, orc):
+    """Mini-batch k-means iterations on SH-like vectors: assignments and counts
+    exact, centers within an FP32 ulp of the oracle's per-sample updates (the
+    library's FP64 running mean differs only by rounding order); every
+    iteration starts both sides from the library's state."""
+    x, cb = synth.vq_data(20_000, 36, 128, seed=4)
+    rng = np.random.default_rng(4)
+    counts = np.zeros(128, np.int64)
+    counts[::3] = 7  # some centers have absorbed samples already
+    xd = dev(torch, x)
+    cbd = dev(torch, cb)
+    cd = dev(torch, counts)
+    for it in range(3):
+        batch = rng.integers(0, x.shape[0], 4096)
+        c0, v0 = host(cbd).copy(), host(cd).copy()
+        a = mgs.kmeans_step(xd, cbd, cd, dev(torch, batch))
+        torch.cuda.synchronize()
+        wc, wv, wa = orc.kmeans_step(x, c0, v0, batch)
+        assert np.array_equal(host(a), wa), it
+        assert np.array_equal(host(cd), wv), it
+        np.testing.assert_allclose(host(cbd), wc, rtol=2.5e-7, atol=1e-9)
+    # an empty batch changes nothing
+    c0 = host(cbd).copy()
+    mgs.kmeans_step(xd, cbd, cd, dev(torch, np.zeros(0, np.int64)))
+    assert np.array_equal(host(cbd), c0)
+    # a row index outside [0, N) is reported
+    with pytest.raises(mgs.MgsError) as e:
+        mgs.kmeans_step(xd, cbd, cd, dev(torch, np.array([0, x.shape[0]], np.int64)))
+    assert e.value.code == mgs.ENONFINITE
+
+
+@pytest.mark.parametrize("remaining", [0, 32 * 36 * 7 + 5, 32 * 36 * 5000, 10 ** 12])
+def test_vq_retain(torch, orc, remaining):
+    """Budget-first retention after the assignment: extended codebook and index
+    table equal the oracle's (copies, so bit for bit)."""
+    x, cb = synth.vq_data(30_000, 36, 256, seed=6)
+    imp = np.random.default_rng(6).lognormal(0, 2, x.shape[0]).astype(np.float32)
+    imp[::97] = imp[0]  # ties
+    idx0, _ = orc.vq_assign(x, cb)
+    idx = dev(torch, idx0)
+    ext, r = mgs.vq_retain(dev(torch, x), dev(torch, imp), dev(torch, cb), idx, remaining)
+    torch.cuda.synchronize()
+    wext, widx, wr = orc.vq_retain(x, imp, cb, idx0, remaining)
+    assert r == wr
+    assert np.array_equal(host(ext), wext)
+    assert np.array_equal(host(idx), widx)

@@ -454,3 +454,57 @@ def test_calibrated_search_ratio_choice(orc):
     assert r["best_t"] == 1 and r["obj"].tolist() == [2.0, 1.0]
     r = orc.search_calibrated(np.concatenate([err, err], axis=0), b2, [20, 20], 10, [4, 8], 250)
     assert r["best_t"] == 1  # tie, equal k: the later ratio
+
+
+# ---------------------------------------------------------------- mini-batch k-means
+def test_kmeans_step_by_hand(orc):
+    """Centers 0 and 10 with one absorbed sample each, batch 1, 2, 9: 1 and 2
+    go to center 0 (learning rates 1/2 then 1/3: 0 -> 0.5 -> 1.0), 9 to
+    center 1 (rate 1/2: 10 -> 9.5)."""
+    x = np.array([[1.0], [2.0], [9.0]], np.float32)
+    cb = np.array([[0.0], [10.0]], np.float32)
+    c, v, a = orc.kmeans_step(x, cb, [1, 1], [0, 1, 2])
+    assert a.tolist() == [0, 0, 1] and v.tolist() == [3, 2]
+    assert c[:, 0].tolist() == [1.0, 9.5]
+    # a center that has absorbed nothing takes its first row, then the mean
+    c, v, a = orc.kmeans_step(x, cb, [0, 5], [1, 0, 1])
+    assert a.tolist() == [0, 0, 0] and v.tolist() == [3, 5]
+    assert c[0, 0] == np.float32(5.0 / 3.0) and c[1, 0] == 10.0
+
+
+def test_kmeans_step_is_the_running_mean(orc):
+    """The per-sample updates of a batch equal the closed form
+    (v c + sum of the center's rows) / (v + n) of the running mean."""
+    rng = np.random.default_rng(8)
+    x = rng.normal(0, 1, (300, 5)).astype(np.float32)
+    cb = x[rng.choice(300, 7, replace=False)].copy()
+    counts = rng.integers(0, 20, 7)
+    batch = rng.integers(0, 300, 120)
+    c, v, a = orc.kmeans_step(x, cb, counts, batch)
+    for j in range(7):
+        rows = x[batch[a == j]].astype(np.float64)
+        assert v[j] == counts[j] + rows.shape[0]
+        if rows.shape[0]:
+            want = (counts[j] * cb[j].astype(np.float64) + rows.sum(0)) / v[j]
+            np.testing.assert_allclose(c[j], want.astype(np.float32), rtol=3e-7, atol=1e-7)
+        else:
+            assert np.array_equal(c[j], cb[j])
+    # the assignment is the exact nearest center of each batch row
+    d = ((x[batch][:, None, :].astype(np.float64) - cb[None].astype(np.float64)) ** 2).sum(-1)
+    assert np.array_equal(a, d.argmin(1))
+
+
+def test_vq_retain_by_hand(orc):
+    """130 remaining bits hold two 2-dim FP32 vectors (64 bits each): the two
+    most important Gaussians (importance 5 at index 4, 4 at index 2) keep
+    their own rows, appended in index order after the K = 3 codewords."""
+    x = np.arange(10, dtype=np.float32).reshape(5, 2)
+    cb = np.full((3, 2), -1.0, np.float32)
+    idx = np.array([0, 1, 2, 0, 1], np.int32)
+    ext, new, r = orc.vq_retain(x, [3, 1, 4, 1, 5], cb, idx, 130)
+    assert r == 2 and new.tolist() == [0, 1, 3, 0, 4]
+    assert ext.tolist() == cb.tolist() + [[4.0, 5.0], [8.0, 9.0]]
+    # equal importance: the lower indices are kept; no budget keeps nothing
+    ext, new, r = orc.vq_retain(x, [1, 1, 1, 1, 1], cb, idx, 128)
+    assert r == 2 and new.tolist() == [3, 4, 2, 0, 1]
+    assert orc.vq_retain(x, [1] * 5, cb, idx, 63)[2] == 0
