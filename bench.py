@@ -280,6 +280,7 @@ def main():
     }
     out["search_variants"] = search_variants(mgs, w, k, G, err_h.numpy(), bits_h.numpy(), budget_bits)
     out["kmeans"] = kmeans_iterations(mgs, torch, sh, cb, s)
+    out["raht"] = raht_timing(mgs, torch, w, attr_h, s)
     if not args.no_plain:
         out["plain_per_candidate"] = plain_sweep(mgs, torch, attr, imp, kept, k, G, w.bits, s, med["sweep"])
     if args.serve_jobs > 0:
@@ -330,6 +331,35 @@ def search_variants(mgs, w, k, G, err, bits, budget_bits):
         out["calibrated"]["obj"] = float(cal["obj"][b])
         out["calibrated"]["actual_over_budget"] = float(cal["actual"][b]) / budget_bits
     return out
+
+
+def raht_timing(mgs, torch, w, attr_h, s, depth: int = 14, reps: int = 3):
+    """RAHT forward and inverse of the workload's attributes (all channels)
+    over seeded clustered voxels of a 2^depth grid, HIP events on the stream;
+    not part of the timed step."""
+    from paper_2604_26799_amd import synth
+    n = w.n
+    coords = synth.voxels(n, depth, seed=w.seed + 2)
+    codes, order = synth.voxel_codes(coords, depth)
+    cd = torch.from_numpy(codes.view(np.int64)).to(torch.device("cuda"))
+    a = torch.from_numpy(np.ascontiguousarray(attr_h[:, order])).cuda()
+    C = a.shape[0]
+    ws = mgs.workspace(mgs.lib().mgs_raht_ws_bytes(n, C, depth), a.device)
+    coef = mgs.raht(cd, a, depth, ws=ws, stream=s)
+    mgs.raht(cd, coef, depth, inverse=True, ws=ws, stream=s)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(s)
+    for _ in range(reps):
+        coef = mgs.raht(cd, a, depth, ws=ws, stream=s, check=False)
+    e[1].record(s)
+    for _ in range(reps):
+        back = mgs.raht(cd, coef, depth, inverse=True, ws=ws, stream=s, check=False)
+    e[2].record(s)
+    e[2].synchronize()
+    err = float((back - a).abs().max())
+    return {"points": n, "channels": C, "depth": depth, "steps": 3 * depth,
+            "forward_ms": e[0].elapsed_time(e[1]) / reps, "inverse_ms": e[1].elapsed_time(e[2]) / reps,
+            "roundtrip_max_abs_err": err}
 
 
 def kmeans_iterations(mgs, torch, x, cb, s, batch_rows: int = 1 << 18, iters: int = 5):

@@ -262,6 +262,39 @@ int mgs_vq_retain(const float* d_x, int64_t N, int32_t D, const int32_t* d_top, 
                   float* d_cb_ext, int32_t K, int32_t* d_idx, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ======================================================================
+ * Region-Adaptive Hierarchical Transform of attributes over voxelized
+ * positions (paper: section "Attribute Transformation", paragraph "Region
+ * Adaptive Hierarchical Transform": transform T_1, leaf weight 1, merged
+ * weight the sum of its children's, unmatched nodes passing up, one DC and
+ * N - 1 AC coefficients per channel).
+ *
+ * d_codes[N]: Morton codes of the occupied voxels (per level: x in bit 0,
+ * y in bit 1, z in bit 2), strictly increasing, below 2^(3 depth), with
+ * depth in [1, 21] bits per axis.  Step s = 0 .. 3 depth - 1 merges every
+ * two live nodes whose codes agree above bit s (the one with bit s clear:
+ * weight w1, value a1; the other: w2, a2):
+ *   L = (sqrt(w1) a1 + sqrt(w2) a2) / sqrt(w1 + w2)   (weight w1 + w2, goes up)
+ *   H = (sqrt(w1) a2 - sqrt(w2) a1) / sqrt(w1 + w2)   (AC coefficient)
+ * in FP64, in that order of operations.  mgs_raht_forward reads d_attr[C][ld]
+ * (attributes in the order of the codes) and writes d_coef[C][ld]: column 0
+ * the DC (the root's value), columns 1 .. N-1 the AC coefficients in the
+ * order they are made (step by step; within a step by Morton code), FP32.
+ * mgs_raht_inverse maps such coefficients back to attributes (the merges are
+ * recomputed from the codes and undone in reverse).  The transform is
+ * orthonormal: sum of squared attributes = sum of squared coefficients, and
+ * the DC is sqrt(N) times the mean.  Workspace: mgs_raht_ws_bytes(N, C,
+ * depth).  Errors: MGS_EINVAL (N outside [1, 2048 * 4096], C < 1, ld < N,
+ * depth outside [1, 21], NULL pointers), MGS_EWORKSPACE; codes that do not
+ * increase or exceed 2^(3 depth) raise MGS_ENONFINITE in the status word
+ * (the coefficients are then unspecified).
+ * ====================================================================== */
+size_t mgs_raht_ws_bytes(int64_t N, int32_t C, int32_t depth);
+int mgs_raht_forward(const uint64_t* d_codes, int64_t N, int32_t C, int32_t depth, const float* d_attr,
+                     int64_t ld, float* d_coef, void* d_ws, size_t ws_bytes, void* stream);
+int mgs_raht_inverse(const uint64_t* d_codes, int64_t N, int32_t C, int32_t depth, const float* d_coef,
+                     int64_t ld, float* d_attr, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ======================================================================
  * Replayable launch sequences (hipGraph).
  *
  * mgs_graph_begin starts capturing `stream` (which must not be the legacy

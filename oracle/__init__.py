@@ -372,3 +372,63 @@ def vq_retain(x, imp, cb, idx, remaining_bits: int):
     ext = np.concatenate([np.asarray(cb, dtype=np.float32), x[top]], axis=0)
     idx[top] = K + np.arange(r, dtype=np.int32)
     return ext, idx, r
+
+
+def morton(coords, depth: int) -> np.ndarray:
+    """Morton code of integer voxel coordinates: bit 3l of the code is bit l
+    of x, bit 3l+1 of y, bit 3l+2 of z."""
+    coords = np.asarray(coords, dtype=np.int64)
+    code = np.zeros(coords.shape[0], dtype=np.uint64)
+    for l in range(depth):
+        for a in range(3):
+            code |= ((coords[:, a] >> l) & 1).astype(np.uint64) << np.uint64(3 * l + a)
+    return code
+
+
+def raht_forward(coords, attr, depth: int):
+    """RAHT (section "Attribute Transformation", paragraph "Region Adaptive
+    Hierarchical Transform"): per level from the finest, along x, then y, then
+    z, every two occupied nodes that differ only in the current axis' bit are
+    merged by T_1 with their weights (leaves 1, merged nodes the sum); the
+    first output goes up, the second is an AC coefficient; unmatched nodes go
+    up unchanged.  Nodes are kept in Morton order (the order of the input,
+    which must be sorted by it), so ACs come out step by step in that order.
+    FP64 as  L = (s1 a1 + s2 a2) / s,  H = (s1 a2 - s2 a1) / s,
+    s1 = sqrt(w1), s2 = sqrt(w2), s = sqrt(w1 + w2).
+    Returns the coefficients f32 [C][N]: DC first, then the ACs.
+    """
+    coords = np.asarray(coords, dtype=np.int64)
+    attr = np.asarray(attr, dtype=np.float32)
+    codes = morton(coords, depth)
+    assert np.all(np.diff(codes.astype(np.float64)) > 0) and np.all(codes[1:] > codes[:-1])
+    C, N = attr.shape
+    nodes = [[tuple(coords[i]), 1, attr[:, i].astype(np.float64)] for i in range(N)]
+    acs = []
+    for level in range(depth):
+        for axis in range(3):
+            new = []
+            i = 0
+            while i < len(nodes):
+                pos, w1, a1 = nodes[i]
+                up = list(pos)
+                up[axis] >>= 1
+                up = tuple(up)
+                if pos[axis] & 1 == 0 and i + 1 < len(nodes):
+                    pos2, w2, a2 = nodes[i + 1]
+                    up2 = list(pos2)
+                    up2[axis] >>= 1
+                    if tuple(up2) == up:
+                        s1, s2, sw = np.sqrt(float(w1)), np.sqrt(float(w2)), np.sqrt(float(w1 + w2))
+                        acs.append((s1 * a2 - s2 * a1) / sw)
+                        new.append([up, w1 + w2, (s1 * a1 + s2 * a2) / sw])
+                        i += 2
+                        continue
+                new.append([up, w1, a1])
+                i += 1
+            nodes = new
+    assert len(nodes) == 1
+    out = np.empty((C, N), dtype=np.float32)
+    out[:, 0] = nodes[0][2]
+    for j, h in enumerate(acs):
+        out[:, 1 + j] = h
+    return out

@@ -61,6 +61,9 @@ SIGNATURES = {
     "mgs_kmeans_step_ws_bytes": (SZ, [I64, I32, I32]),
     "mgs_kmeans_step": (ct.c_int, [P, I64, I32, P, I64, P, I32, P, P, P, SZ, P]),
     "mgs_vq_retain_count": (I64, [I64, I64, I32]),
+    "mgs_raht_ws_bytes": (SZ, [I64, I32, I32]),
+    "mgs_raht_forward": (ct.c_int, [P, I64, I32, I32, P, I64, P, P, SZ, P]),
+    "mgs_raht_inverse": (ct.c_int, [P, I64, I32, I32, P, I64, P, P, SZ, P]),
     "mgs_vq_retain": (ct.c_int, [P, I64, I32, P, I64, P, I32, P, P, SZ, P]),
     "mgs_graph_begin": (ct.c_int, [P]),
     "mgs_graph_end": (ct.c_int, [P, ct.POINTER(ct.c_void_p)]),
@@ -412,6 +415,22 @@ def vq_retain(x, imp, cb, idx, remaining_bits: int, ws=None, stream=None, check:
                                ws.numel(), _stream(stream)), "mgs_vq_retain")
     _finish(ws, check, "mgs_vq_retain", stream)
     return cb_ext, r
+
+
+def raht(codes, values, depth: int, inverse: bool = False, ws=None, stream=None, check: bool = True):
+    """RAHT of ``values`` (f32 [C][N], order of the Morton ``codes`` u64/i64 [N])
+    or, with ``inverse``, back from coefficients; returns f32 [C][N]."""
+    torch = _torch()
+    C, N = values.shape
+    need = lib().mgs_raht_ws_bytes(N, C, depth)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, values.device)
+    out = torch.empty((C, N), dtype=torch.float32, device=values.device)
+    fn = lib().mgs_raht_inverse if inverse else lib().mgs_raht_forward
+    _check(fn(_dptr(codes), N, C, depth, _dptr(values), N, _dptr(out), _dptr(ws), ws.numel(), _stream(stream)),
+           "mgs_raht_inverse" if inverse else "mgs_raht_forward")
+    _finish(ws, check, "mgs_raht", stream)
+    return out
 
 
 # ----------------------------------------------------------------- host side

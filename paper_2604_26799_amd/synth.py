@@ -66,6 +66,36 @@ def ratios_uniform(lo: Fraction, hi: Fraction, count: int) -> List[Fraction]:
     return [lo + i * step for i in range(count)]
 
 
+def voxels(n: int, depth: int, seed: int = 0, clusters: int = 8):
+    """``n`` distinct occupied voxels of a 2^depth grid, clustered like the
+    surfaces of a scene (Gaussian blobs around random centers), as integer
+    coordinates i64 [n][3] in random order."""
+    rng = np.random.default_rng(seed)
+    side = 1 << depth
+    assert n <= side ** 3 // 2
+    centers = rng.integers(0, side, (clusters, 3))
+    out = np.empty((0, 3), np.int64)
+    while out.shape[0] < n:
+        c = centers[rng.integers(0, clusters, 2 * n)]
+        p = np.rint(c + rng.normal(0, side / 8, (2 * n, 3))).astype(np.int64) % side
+        out = np.unique(np.concatenate([out, p]), axis=0)
+    return out[rng.permutation(out.shape[0])[:n]]
+
+
+def voxel_codes(coords, depth: int):
+    """Morton codes of voxel coordinates (bit 3l + a holds bit l of axis a,
+    x = 0, y = 1, z = 2), sorted, with the permutation that sorts them: the
+    octree order in which positions reach the attribute transform."""
+    coords = np.asarray(coords, dtype=np.uint64)
+    code = np.zeros(coords.shape[0], dtype=np.uint64)
+    one = np.uint64(1)
+    for l in range(depth):
+        for a in range(3):
+            code |= ((coords[:, a] >> np.uint64(l)) & one) << np.uint64(3 * l + a)
+    order = np.argsort(code, kind="stable")
+    return code[order], order
+
+
 def vq_data(n: int, dim: int = 36, k: int = 4096, seed: int = 0):
     """Higher-degree SH vectors ~ Laplace(0, 0.03) and a codebook drawn from them.
 

@@ -491,3 +491,32 @@ def test_vq_retain(torch, orc, remaining):
     assert r == wr
     assert np.array_equal(host(ext), wext)
     assert np.array_equal(host(idx), widx)
+
+
+@pytest.mark.parametrize("n,depth,C", [(1, 4, 2), (3, 1, 1), (2000, 6, 3), (6000, 10, 2)])
+def test_raht(torch, orc, n, depth, C):
+    """RAHT forward: every coefficient bit-identical to the oracle (same FP64
+    operations, FP32 storage); inverse: back to the attributes within FP32
+    rounding, also from the oracle's coefficients."""
+    from paper_2604_26799_amd import synth
+    coords = synth.voxels(n, depth, seed=n) if n > 3 else np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]])[:n]
+    codes = orc.morton(coords, depth)
+    order = np.argsort(codes)
+    coords, codes = coords[order], codes[order]
+    a = np.random.default_rng(n).normal(0, 1, (C, n)).astype(np.float32)
+    cd = dev(torch, codes.view(np.int64))
+    got = mgs.raht(cd, dev(torch, a), depth)
+    torch.cuda.synchronize()
+    want = orc.raht_forward(coords, a, depth)
+    assert np.array_equal(host(got), want)
+    back = host(mgs.raht(cd, got, depth, inverse=True))
+    np.testing.assert_allclose(back, a, rtol=1e-5, atol=1e-5)
+    back2 = host(mgs.raht(cd, dev(torch, want), depth, inverse=True))
+    np.testing.assert_allclose(back2, a, rtol=1e-5, atol=1e-5)
+
+
+def test_raht_rejects_unsorted_codes(torch, orc):
+    codes = np.array([3, 1, 2], np.int64)
+    with pytest.raises(mgs.MgsError) as e:
+        mgs.raht(dev(torch, codes), dev(torch, np.ones((1, 3), np.float32)), 2)
+    assert e.value.code == mgs.ENONFINITE

@@ -508,3 +508,33 @@ def test_vq_retain_by_hand(orc):
     ext, new, r = orc.vq_retain(x, [1, 1, 1, 1, 1], cb, idx, 128)
     assert r == 2 and new.tolist() == [3, 4, 2, 0, 1]
     assert orc.vq_retain(x, [1] * 5, cb, idx, 63)[2] == 0
+
+
+# ----------------------------------------------------------------------- RAHT
+def test_raht_paper_example(orc):
+    """The paper's 2-D example: a1 = 1 at (0, 0) and a2 = 3 at (1, 0) merge along
+    x (weights 1, 1): d1 = 4/sqrt 2, c1 = 2/sqrt 2 = sqrt 2; then d1 (weight 2)
+    and a0 = 5 at (0, 1) along y: d2 = (sqrt 2 d1 + 5)/sqrt 3 = 3 sqrt 3,
+    c2 = (sqrt 2 * 5 - d1)/sqrt 3 = sqrt 6.  One DC and two ACs."""
+    coords = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]])
+    assert orc.morton(coords, 1).tolist() == [0, 1, 2]
+    out = orc.raht_forward(coords, np.array([[1.0, 3.0, 5.0]], np.float32), 1)
+    np.testing.assert_allclose(out[0], [3 * math.sqrt(3), math.sqrt(2), math.sqrt(6)], rtol=1e-7)
+    # one leaf: its value is the DC
+    assert orc.raht_forward(np.array([[5, 2, 7]]), np.array([[2.5]], np.float32), 3).tolist() == [[2.5]]
+
+
+def test_raht_invariants(orc):
+    """Orthonormal: the energy is preserved and the DC is sqrt(N) times the mean;
+    a constant attribute has (numerically) zero AC coefficients."""
+    from paper_2604_26799_amd import synth
+    coords = synth.voxels(700, 5, seed=3)
+    coords = coords[np.argsort(orc.morton(coords, 5))]
+    rng = np.random.default_rng(3)
+    a = rng.normal(0, 1, (2, 700)).astype(np.float32)
+    out = orc.raht_forward(coords, a, 5).astype(np.float64)
+    a64 = a.astype(np.float64)
+    np.testing.assert_allclose((out ** 2).sum(1), (a64 ** 2).sum(1), rtol=1e-5)
+    np.testing.assert_allclose(out[:, 0], math.sqrt(700) * a64.mean(1), rtol=1e-5)
+    const = orc.raht_forward(coords, np.full((1, 700), 2.0, np.float32), 5)
+    assert np.abs(const[0, 1:]).max() < 1e-5 and const[0, 0] == pytest.approx(2.0 * math.sqrt(700), rel=1e-6)
