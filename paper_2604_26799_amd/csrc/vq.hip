@@ -334,21 +334,22 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
 }
 
 // Exact FP64 full scan for the rows whose candidate buffer overflowed: one
-// wavefront per row, lanes stride over the codewords.
+// workgroup per row (all four waves stride over the codewords, then the
+// smallest (distance, index) over the workgroup), rows strided over the grid.
 __global__ __launch_bounds__(256) void vq_fallback_kernel(VqArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * 4;
+    __shared__ double wbest[4];
+    __shared__ int32_t wj[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t total = *a.fb_count;
     if (a.nfb_out && blockIdx.x == 0 && threadIdx.x == 0) *a.nfb_out = (int64_t)total;
-    for (int64_t i = wid; i < total; i += nw) {
+    for (int64_t i = blockIdx.x; i < total; i += gridDim.x) {  // uniform over the workgroup
         const int32_t r = a.fb_list[i];
         const float* xr = a.x + (int64_t)r * a.D;
         double best = INFINITY;
         int32_t bj = 0x7fffffff;
-        for (int j = lane; j < a.K; j += 64) {
+        for (int j = threadIdx.x; j < a.K; j += 256) {
             const double d = exact_dist(xr, a.cb + (int64_t)j * a.D, a.D);
-            if (d < best) {  // j increases per lane: strict < keeps the smallest j
+            if (d < best) {  // j increases per thread: strict < keeps the smallest j
                 best = d;
                 bj = j;
             }
@@ -363,9 +364,20 @@ __global__ __launch_bounds__(256) void vq_fallback_kernel(VqArgs a) {
             }
         }
         if (lane == 0) {
+            wbest[wave] = best;
+            wj[wave] = bj;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < 4; ++w)
+                if (wbest[w] < best || (wbest[w] == best && wj[w] < bj)) {
+                    best = wbest[w];
+                    bj = wj[w];
+                }
             a.idx[r] = bj;
             if (a.dist) a.dist[r] = best;
         }
+        __syncthreads();
     }
 }
 
@@ -441,6 +453,6 @@ extern "C" int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float
             default: hipLaunchKernelGGL(vq_main_kernel<5>, dim3(blocks), dim3(VQ_THREADS), 0, s, a); break;
         }
     }
-    hipLaunchKernelGGL(vq_fallback_kernel, dim3(512), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(vq_fallback_kernel, dim3(2048), dim3(256), 0, s, a);
     return mgs_last_launch();
 }
