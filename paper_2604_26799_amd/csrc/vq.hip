@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "common.h"
 
@@ -60,6 +61,7 @@ struct VqArgs {
     int32_t* fb_list;
     int64_t N;
     int32_t D, K, Kpad, KP;
+    int32_t xvec;         // D % 4 == 0 and x 16-byte aligned: rows load as float4
 };
 
 // Prepared codebook and the codeword-norm maximum (the status word, the
@@ -117,12 +119,18 @@ __device__ __forceinline__ double exact_dist(const float* __restrict__ x, const 
 }
 
 template <int KS>
-__global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
+// Four waves per SIMD (at most 128 VGPRs) for D <= 46; wider rows take three.
+__global__ __launch_bounds__(VQ_THREADS) __attribute__((amdgpu_waves_per_eu(KS <= 3 ? 4 : 3)))
+void vq_main_kernel(VqArgs a) {
     constexpr int KP = 16 * KS;
     constexpr int UNITS = KP / 8;  // 16-byte units per prepared codeword
     // two chunk buffers, filled by direct global-to-LDS loads (64 lanes x 16
-    // contiguous bytes per instruction, so the rows are not padded)
-    __shared__ __attribute__((aligned(16))) __bf16 cbs[2][VQ_CHUNK * KP];
+    // contiguous bytes per instruction, so the rows are not padded).  They are
+    // two variables and every chunk step reads a fixed one, so the compiler
+    // can tell that the copy into one buffer leaves the other alone and does
+    // not wait for the copy before reading.
+    __shared__ __attribute__((aligned(16))) __bf16 cbs0[VQ_CHUNK * KP];
+    __shared__ __attribute__((aligned(16))) __bf16 cbs1[VQ_CHUNK * KP];
     // candidate tiles: tile index and the mask of the lane's codewords in it
     __shared__ int32_t cand_t[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
     __shared__ uint16_t cand_m[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
@@ -142,22 +150,58 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
         const int64_t r = row0 + rs * 32 + (lane & 31);
         float n2 = 0.0f;
+        if (a.xvec) {
+            // D % 4 == 0 and 16-byte aligned rows: every group of 4 dims is one
+            // unconditional float4 load from an in-bounds address (row and
+            // group clamped), all issued before any is used; values outside
+            // the row (padding dims, rows past N) are then selected away
+            const int64_t rr = r < a.N ? r : a.N - 1;
+            float4 t[KS][2];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
+            for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = 16 * ks + 8 * half + i;
-                float v = 0.0f;
-                if (r < a.N) {
-                    if (k < D) {
-                        v = a.x[r * D + k];
-                        bad |= (uint32_t)!finite_f32(v);
-                        n2 += v * v;
-                    } else if (k == D || k == D + 1) {
-                        v = 1.0f;
-                    }
+                for (int h = 0; h < 2; ++h) {
+                    const int k0 = 16 * ks + 8 * half + 4 * h;
+                    const int kk = k0 < D ? k0 : D - 4;
+                    t[ks][h] = *(const float4*)(a.x + rr * D + kk);
                 }
-                breg[rs][ks][i] = (__bf16)v;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 16 * ks + 8 * half + i;
+                    const float4 q = t[ks][i >> 2];
+                    const float e = (i & 3) == 0 ? q.x : (i & 3) == 1 ? q.y : (i & 3) == 2 ? q.z : q.w;
+                    float v = 0.0f;
+                    if (r < a.N) {
+                        if (k < D) {
+                            v = e;
+                            bad |= (uint32_t)!finite_f32(v);
+                            n2 += v * v;
+                        } else if (k == D || k == D + 1) {
+                            v = 1.0f;
+                        }
+                    }
+                    breg[rs][ks][i] = (__bf16)v;
+                }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 16 * ks + 8 * half + i;
+                    float v = 0.0f;
+                    if (r < a.N) {
+                        if (k < D) {
+                            v = a.x[r * D + k];
+                            bad |= (uint32_t)!finite_f32(v);
+                            n2 += v * v;
+                        } else if (k == D || k == D + 1) {
+                            v = 1.0f;
+                        }
+                    }
+                    breg[rs][ks][i] = (__bf16)v;
+                }
             }
         }
         n2 += __shfl_xor(n2, 32, MGS_WAVE);
@@ -181,11 +225,11 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
     }
 
     // Asynchronous copy of chunk c0 of the prepared codebook into buffer
-    // `buf`: wave w moves units [(i*VQ_WAVES + w)*64, +64) of the chunk; the
+    // `dst`: wave w moves units [(i*VQ_WAVES + w)*64, +64) of the chunk; the
     // LDS base of each instruction is uniform over the wave.
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-    auto prefetch = [&](int c0, int buf) {
-        const int nunits = min(VQ_CHUNK, a.Kpad - c0) * UNITS;
+    auto prefetch = [&](int c0, __bf16* dst) {
+        constexpr int nunits = VQ_CHUNK * UNITS;  // Kpad is a whole number of chunks
         const char* src = (const char*)(a.cbp + (int64_t)c0 * KP);
 #pragma unroll
         for (int i = 0; i < (VQ_CHUNK * UNITS + VQ_THREADS - 1) / VQ_THREADS; ++i) {
@@ -193,100 +237,113 @@ __global__ __launch_bounds__(VQ_THREADS) void vq_main_kernel(VqArgs a) {
             if (ublk + lane < nunits)
                 __builtin_amdgcn_global_load_lds(
                     (const void*)(src + (size_t)(ublk + lane) * 16),
-                    (__attribute__((address_space(3))) void*)((char*)&cbs[buf][0] + ublk * 16), 16, 0, 0);
+                    (__attribute__((address_space(3))) void*)((char*)dst + ublk * 16), 16, 0, 0);
         }
     };
-    const int nchunks = (a.Kpad + VQ_CHUNK - 1) / VQ_CHUNK;
-    prefetch(0, 0);
+    const int nchunks = a.Kpad / VQ_CHUNK;
+    // The two passes are one sequence of 2 * nchunks chunk steps q (pass 0:
+    // minimum score per lane; pass 1: codewords under the threshold); step q
+    // reads buffer q % 2 while the next chunk is copied into the other one.
+    auto chunk = [&](auto pass_tag, int q, const __bf16* cb_l, __bf16* other) {
+        constexpr bool pass0 = decltype(pass_tag)::value;
+        const int c0 = (pass0 ? q : q - nchunks) * VQ_CHUNK;
+        // the other buffer was last read before the barrier that ended the
+        // previous step: fill it with the next chunk (pass 1 restarts at
+        // chunk 0) while this one is processed
+        if (q + 1 < 2 * nchunks) prefetch(q + 1 == nchunks ? 0 : c0 + VQ_CHUNK, other);
+        // scores of one 32-codeword tile for the wave's row sets; K steps
+        // outer, row sets inner: consecutive MFMAs are independent
+        auto scores = [&](int tile, f32x16 (&acc)[VQ_ROWSETS]) {
+            bf16x8 areg[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                areg[ks] = *(const bf16x8*)(cb_l + (tile * 32 + (lane & 31)) * KP + 16 * ks + 8 * half);
+#pragma unroll
+            for (int rs = 0; rs < VQ_ROWSETS; ++rs) acc[rs] = f32x16{};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int rs = 0; rs < VQ_ROWSETS; ++rs)
+                    acc[rs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(areg[ks], breg[rs][ks], acc[rs], 0, 0, 0);
+        };
+        auto epilogue = [&](int tile, const f32x16 (&acc)[VQ_ROWSETS]) {
+            const int jbase = c0 + tile * 32;
+#pragma unroll
+            for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
+                if constexpr (pass0) {
+                    float tmin = acc[rs][0];
+#pragma unroll
+                    for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
+                    thr[rs] = fminf(thr[rs], tmin);  // pass 0 keeps the lane minimum here
+                } else {
+                    float tmin = acc[rs][0];
+#pragma unroll
+                    for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
+                    if (tmin > thr[rs]) continue;  // most lane-tiles hold no candidate
+                    // sign bits of thr - s, shifted in by v_alignbit (element i
+                    // lands in bit 15 - i); s <= thr  <=>  thr - s >= 0 (an exact
+                    // zero difference is +0), so the mask is the complement
+                    uint32_t neg = 0;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(thr[rs] - acc[rs][i]), 31);
+                    const uint32_t bits = ~neg & 0xFFFFu;
+                    if (cnt[rs] < VQ_CAND) {
+                        cand_t[wave][rs][cnt[rs]][lane] = jbase;
+                        cand_m[wave][rs][cnt[rs]][lane] = (uint16_t)bits;
+                    }
+                    cnt[rs] += 1;  // a count past VQ_CAND marks the overflow
+                }
+            }
+        };
+        // software pipeline: the next tile's MFMAs are issued before this
+        // tile's epilogue, so the matrix cores work while the VALU does
+        // (two accumulator sets, alternating)
+        constexpr int ntiles = VQ_CHUNK / 32;
+        f32x16 acc0[VQ_ROWSETS], acc1[VQ_ROWSETS];
+        scores(0, acc0);
+        int tile = 0;
+        for (; tile + 2 < ntiles; tile += 2) {
+            scores(tile + 1, acc1);
+            epilogue(tile, acc0);
+            scores(tile + 2, acc0);
+            epilogue(tile + 1, acc1);
+        }
+        if (tile + 1 < ntiles) {
+            scores(tile + 1, acc1);
+            epilogue(tile, acc0);
+            epilogue(tile + 1, acc1);
+        } else {
+            epilogue(tile, acc0);
+        }
+        // the step's MFMAs are issued before the wait (the scheduler would
+        // otherwise hoist the wait over them and expose the copy's latency)
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next chunk has landed
+        __syncthreads();                // ... and everyone's; this buffer is free
+    };
+    prefetch(0, cbs0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    // pass 0: minimum score per lane; pass 1: codewords under the threshold
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int ci = 0; ci < nchunks; ++ci) {
-            const int buf = (pass * nchunks + ci) & 1;
-            const int c0 = ci * VQ_CHUNK;
-            const int nrows = min(VQ_CHUNK, a.Kpad - c0);
-            // the other buffer was last read before the barrier that ended
-            // the previous chunk: fill it with the next chunk (pass 1 restarts
-            // at chunk 0) while this one is processed
-            if (ci + 1 < nchunks) prefetch(c0 + VQ_CHUNK, buf ^ 1);
-            else if (pass == 0) prefetch(0, buf ^ 1);
-            const __bf16* cb_l = &cbs[buf][0];
-            // scores of one 32-codeword tile for the wave's row sets; K steps
-            // outer, row sets inner: consecutive MFMAs are independent
-            auto scores = [&](int tile, f32x16 (&acc)[VQ_ROWSETS]) {
-                bf16x8 areg[KS];
+    // step q reads buffer q % 2; each pass has its own code (no per-tile
+    // branch on the pass)
+    const std::integral_constant<bool, true> P0;
+    const std::integral_constant<bool, false> P1;
+    int q = 0;
+    for (; q + 1 < nchunks; q += 2) {
+        chunk(P0, q, cbs0, cbs1);
+        chunk(P0, q + 1, cbs1, cbs0);
+    }
+    if (q < nchunks) chunk(P0, q++, cbs0, cbs1);
+    // end of pass 0: row minimum (the partner lane holds the other 16
+    // codewords of every tile) plus the bound
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-                    areg[ks] = *(const bf16x8*)(cb_l + (tile * 32 + (lane & 31)) * KP + 16 * ks + 8 * half);
-#pragma unroll
-                for (int rs = 0; rs < VQ_ROWSETS; ++rs) acc[rs] = f32x16{};
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                    for (int rs = 0; rs < VQ_ROWSETS; ++rs)
-                        acc[rs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(areg[ks], breg[rs][ks], acc[rs], 0, 0, 0);
-            };
-            auto epilogue = [&](int tile, const f32x16 (&acc)[VQ_ROWSETS]) {
-                const int jbase = c0 + tile * 32;
-#pragma unroll
-                for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-                    if (pass == 0) {
-                        float tmin = acc[rs][0];
-#pragma unroll
-                        for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
-                        thr[rs] = fminf(thr[rs], tmin);  // pass 0 keeps the lane minimum here
-                    } else {
-                        float tmin = acc[rs][0];
-#pragma unroll
-                        for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
-                        if (tmin > thr[rs]) continue;  // most lane-tiles hold no candidate
-                        // sign bits of thr - s, shifted in by v_alignbit (element i
-                        // lands in bit 15 - i); s <= thr  <=>  thr - s >= 0 (an exact
-                        // zero difference is +0), so the mask is the complement
-                        uint32_t neg = 0;
-#pragma unroll
-                        for (int i = 0; i < 16; ++i)
-                            neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(thr[rs] - acc[rs][i]), 31);
-                        const uint32_t bits = ~neg & 0xFFFFu;
-                        if (cnt[rs] < VQ_CAND) {
-                            cand_t[wave][rs][cnt[rs]][lane] = jbase;
-                            cand_m[wave][rs][cnt[rs]][lane] = (uint16_t)bits;
-                        }
-                        cnt[rs] += 1;  // a count past VQ_CAND marks the overflow
-                    }
-                }
-            };
-            // software pipeline: the next tile's MFMAs are issued before this
-            // tile's epilogue, so the matrix cores work while the VALU does
-            // (two accumulator sets, alternating)
-            const int ntiles = nrows / 32;
-            f32x16 acc0[VQ_ROWSETS], acc1[VQ_ROWSETS];
-            scores(0, acc0);
-            int tile = 0;
-            for (; tile + 2 < ntiles; tile += 2) {
-                scores(tile + 1, acc1);
-                epilogue(tile, acc0);
-                scores(tile + 2, acc0);
-                epilogue(tile + 1, acc1);
-            }
-            if (tile + 1 < ntiles) {
-                scores(tile + 1, acc1);
-                epilogue(tile, acc0);
-                epilogue(tile + 1, acc1);
-            } else {
-                epilogue(tile, acc0);
-            }
-            __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next chunk has landed
-            __syncthreads();                // ... and everyone's; this buffer is free
-        }
-        if (pass == 0) {
-            // row minimum (the partner lane holds the other 16 codewords of
-            // every tile) plus the bound
-#pragma unroll
-            for (int rs = 0; rs < VQ_ROWSETS; ++rs)
-                thr[rs] = fminf(thr[rs], __shfl_xor(thr[rs], 32, MGS_WAVE)) + T[rs];
-        }
+    for (int rs = 0; rs < VQ_ROWSETS; ++rs)
+        thr[rs] = fminf(thr[rs], __shfl_xor(thr[rs], 32, MGS_WAVE)) + T[rs];
+    if (q & 1) chunk(P1, q++, cbs1, cbs0);
+    for (; q + 1 < 2 * nchunks; q += 2) {
+        chunk(P1, q, cbs0, cbs1);
+        chunk(P1, q + 1, cbs1, cbs0);
     }
 
     // ---- exact FP64 re-rank of the row's candidates (both lanes of the row)
@@ -390,7 +447,8 @@ VqLayout vq_layout(int64_t N, int D, int K) {
     VqLayout L;
     L.KS = (D + 2 + 15) / 16;
     L.KP = 16 * L.KS;
-    L.Kpad = (int)(((int64_t)K + 31) / 32 * 32);
+    // whole chunks: padding codewords score ~1e30 and never become candidates
+    L.Kpad = (int)(((int64_t)K + VQ_CHUNK - 1) / VQ_CHUNK * VQ_CHUNK);
     size_t o = MGS_STATUS_BYTES;
     L.cmax = o;
     o += 256;
@@ -438,6 +496,7 @@ extern "C" int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float
     a.K = K;
     a.Kpad = L.Kpad;
     a.KP = L.KP;
+    a.xvec = (D % 4 == 0) && ((uintptr_t)d_x % 16 == 0);
     int rc = mgs_fill<uint32_t>((uint32_t*)ws, 64, 0u, s);       // status word
     if (rc) return rc;
     rc = mgs_fill<uint32_t>(a.cmax_bits, 64, 0u, s);              // norm maximum + fallback count
