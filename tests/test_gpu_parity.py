@@ -405,7 +405,8 @@ def test_sweep_codes_match_quantize(torch, orc):
 # ------------------------------------------------------------------ VQ
 @pytest.mark.parametrize("n,D,K,seed", [
     (5000, 36, 4096, 0), (3000, 36, 100, 1), (2000, 1, 7, 2), (777, 5, 1, 3),
-    (4000, 46, 333, 4), (1000, 64, 50, 5), (64, 36, 32, 6), (0, 36, 10, 7)])
+    (4000, 46, 333, 4), (1000, 64, 50, 5), (64, 36, 32, 6), (0, 36, 10, 7),
+    (1500, 8, 77, 8), (1200, 12, 64, 9)])
 def test_vq_small(torch, orc, n, D, K, seed):
     rng = np.random.default_rng(seed)
     x = rng.laplace(0, 0.03, (n, D)).astype(np.float32)
@@ -413,6 +414,24 @@ def test_vq_small(torch, orc, n, D, K, seed):
     if n >= K:
         cb[: K // 2] = x[rng.choice(n, K // 2, replace=False)]
     idx, dist, nfb = mgs.vq_assign(dev(torch, x), dev(torch, cb))
+    want_i, want_d = orc.vq_assign(x, cb)
+    np.testing.assert_array_equal(host(idx), want_i)
+    np.testing.assert_array_equal(host(dist), want_d)
+
+
+@pytest.mark.parametrize("D", [36, 8])
+def test_vq_unaligned_rows(torch, orc, D):
+    """Rows that start 4 bytes past a 16-byte boundary take the per-element load
+    path (the float4 path needs D % 4 == 0 and aligned rows); same results."""
+    rng = np.random.default_rng(12)
+    n, K = 2500, 300
+    x = rng.laplace(0, 0.03, (n, D)).astype(np.float32)
+    cb = rng.laplace(0, 0.03, (K, D)).astype(np.float32)
+    buf = torch.zeros(n * D + 1, dtype=torch.float32, device="cuda")
+    buf[1:].copy_(torch.from_numpy(x.reshape(-1)))
+    xv = buf[1:].view(n, D)
+    assert xv.data_ptr() % 16 == 4
+    idx, dist, _ = mgs.vq_assign(xv, dev(torch, cb))
     want_i, want_d = orc.vq_assign(x, cb)
     np.testing.assert_array_equal(host(idx), want_i)
     np.testing.assert_array_equal(host(dist), want_d)
