@@ -13,9 +13,12 @@
 // one histogram pass over the importance per digit, each followed by a tiny
 // per-k kernel that picks the digit holding the k-th key.  Passes after the
 // first only count keys that still match a k's prefix, found through an LDS
-// table indexed by the top digit.  A compaction then writes each kept set
-// in index order: per-block counts, a per-k scan over blocks, and a write
-// pass that ranks kept elements with wavefront ballots.
+// table indexed by the top digit.  A k whose key is the last of its digit
+// bucket is resolved there (every lower threshold bit set), and a pass with
+// no unresolved k exits at once: without ties across the k-th key the index
+// digits cost nothing.  A compaction then writes each kept set in index
+// order: per-(chunk, k) counts, a per-k scan over chunks, and a write pass
+// per (chunk, k) that ranks kept elements with wavefront ballots.
 #include <algorithm>
 #include <cstring>
 
@@ -35,7 +38,7 @@ constexpr int PR_BITS[PR_LEVELS] = {11, 11, 10, 11, 11, 10};
 
 struct PruneState {
     uint64_t prefix;  // key bits fixed so far (above the current digit)
-    int64_t rem;      // rank (1-based) of the wanted key within that prefix
+    int64_t rem;      // rank (1-based) of the wanted key within that prefix; 0: resolved
 };
 
 struct PruneArgs {
@@ -100,19 +103,25 @@ __global__ __launch_bounds__(PR_HIST_THREADS) void prune_hist_kernel(PruneArgs a
     __shared__ uint64_t pre[MGS_MAX_RATIOS];
     for (int i = threadIdx.x; i < PR_BINS; i += PR_HIST_THREADS) first[i] = -1;
     __syncthreads();
+    __shared__ int active;
     const int hs = PR_SHIFT[level - 1];  // bits at and above this shift are fixed
     if (threadIdx.x < a.T && a.k[threadIdx.x] > 0) pre[threadIdx.x] = a.state[threadIdx.x].prefix >> hs;
     __syncthreads();
-    // Build the per-top-digit lists serially (T <= 64 entries).
+    // Build the per-top-digit lists serially (T <= 64 entries) of the k whose
+    // key is not resolved yet.
     if (threadIdx.x == 0) {
+        int na = 0;
         for (int t = a.T - 1; t >= 0; --t) {
-            if (a.k[t] <= 0) continue;
+            if (a.k[t] <= 0 || a.state[t].rem == 0) continue;
             uint32_t d0 = (uint32_t)(a.state[t].prefix >> PR_SHIFT[0]);
             next[t] = first[d0];
             first[d0] = (int16_t)t;
+            ++na;
         }
+        active = na;
     }
     __syncthreads();
+    if (active == 0) return;  // every k resolved at an earlier digit (no tie across it)
     for (int64_t i = (int64_t)blockIdx.x * PR_HIST_THREADS + threadIdx.x; i < a.n;
          i += (int64_t)gridDim.x * PR_HIST_THREADS) {
         uint64_t ck = comp_key(a.imp, i);
@@ -130,9 +139,10 @@ __global__ __launch_bounds__(PR_HIST_THREADS) void prune_hist_kernel(PruneArgs a
 __global__ __launch_bounds__(256) void prune_select_kernel(PruneArgs a, int level) {
     const int t = blockIdx.x;
     if (a.k[t] <= 0) return;
+    if (level > 0 && a.state[t].rem == 0) return;  // resolved
     __shared__ uint32_t part[256];
     __shared__ int64_t found_base;
-    __shared__ uint32_t found_digit;
+    __shared__ uint32_t found_digit, found_count;
     const uint32_t* h = level_hist(a, level, t);
     const int nbins = 1 << PR_BITS[level];
     const int per = PR_BINS / 256;  // 8 bins per thread (only the first nbins used)
@@ -158,6 +168,7 @@ __global__ __launch_bounds__(256) void prune_select_kernel(PruneArgs a, int leve
             if (cum + c >= st.rem) {
                 found_digit = (uint32_t)(b0 + j);
                 found_base = cum;
+                found_count = c;
                 break;
             }
             cum += c;
@@ -171,38 +182,40 @@ __global__ __launch_bounds__(256) void prune_select_kernel(PruneArgs a, int leve
     if (threadIdx.x == 0) {
         st.prefix |= (uint64_t)found_digit << PR_SHIFT[level];
         st.rem -= found_base;
+        if (st.rem == (int64_t)found_count) {
+            // the wanted key is the last of its bucket: the whole bucket is
+            // kept, and no other key lies between, so the threshold can take
+            // every lower bit set (with distinct importances this happens
+            // once the importance digits are fixed, and the index digits
+            // need no pass)
+            st.prefix |= (PR_SHIFT[level] ? (1ull << PR_SHIFT[level]) - 1ull : 0ull);
+            st.rem = 0;
+        }
         a.state[t] = st;
     }
 }
 
-// Compaction, phase counts: kept keys of every k in each block's chunk.
+// Compaction, phase counts: kept keys of one k (blockIdx.y) in one chunk.
 __global__ __launch_bounds__(PR_CHUNK_THREADS) void prune_count_kernel(PruneArgs a) {
-    __shared__ uint64_t thr[MGS_MAX_RATIOS];
-    __shared__ uint32_t wsum[MGS_MAX_RATIOS][PR_CHUNK_THREADS / MGS_WAVE];
+    __shared__ uint32_t wsum[PR_CHUNK_THREADS / MGS_WAVE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x < a.T) thr[threadIdx.x] = a.state[threadIdx.x].prefix;
-    __syncthreads();
+    const int t = blockIdx.y;
+    if (a.k[t] <= 0) return;  // its counts are never read
+    const uint64_t th = a.state[t].prefix;
     const int64_t base = (int64_t)blockIdx.x * PR_CHUNK;
-    uint64_t ck[PR_CHUNK_ROUNDS];
+    uint32_t c = 0;
 #pragma unroll
     for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
         int64_t i = base + r * PR_CHUNK_THREADS + threadIdx.x;
-        ck[r] = i < a.n ? comp_key(a.imp, i) : ~0ull;
+        const uint64_t ck = i < a.n ? comp_key(a.imp, i) : ~0ull;
+        c += (uint32_t)__popcll(__ballot(ck <= th));
     }
-    for (int t = 0; t < a.T; ++t) {
-        uint32_t c = 0;
-        if (a.k[t] > 0) {
-            const uint64_t th = thr[t];
-#pragma unroll
-            for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) c += (uint32_t)__popcll(__ballot(ck[r] <= th));
-        }
-        if (lane == 0) wsum[t][wave] = c;
-    }
+    if (lane == 0) wsum[wave] = c;
     __syncthreads();
-    if (threadIdx.x < a.T) {
+    if (threadIdx.x == 0) {
         uint32_t s = 0;
-        for (int w = 0; w < PR_CHUNK_THREADS / MGS_WAVE; ++w) s += wsum[threadIdx.x][w];
-        a.cnt[(int64_t)threadIdx.x * a.nblk + blockIdx.x] = s;
+        for (int w = 0; w < PR_CHUNK_THREADS / MGS_WAVE; ++w) s += wsum[w];
+        a.cnt[(int64_t)t * a.nblk + blockIdx.x] = s;
     }
 }
 
@@ -232,51 +245,50 @@ __global__ __launch_bounds__(1024) void prune_scan_kernel(PruneArgs a) {
     }
 }
 
-// Compaction, phase write: each kept key's position is its block's offset,
-// plus the kept keys of earlier (round, wave) pairs, plus the lanes below.
+// Compaction, phase write, one block per (chunk, k): each kept key's position
+// is the chunk's offset, plus the kept keys of earlier (round, wave) pairs
+// (an exclusive scan of the 64 ballot counts by one wavefront), plus the
+// lanes below.
 __global__ __launch_bounds__(PR_CHUNK_THREADS) void prune_write_kernel(PruneArgs a) {
     constexpr int NW = PR_CHUNK_THREADS / MGS_WAVE;
-    __shared__ uint64_t thr[MGS_MAX_RATIOS];
-    __shared__ uint32_t off[PR_CHUNK_ROUNDS][NW];
+    static_assert(PR_CHUNK_ROUNDS * NW == MGS_WAVE, "one count per lane of the scanning wavefront");
+    __shared__ uint32_t off[PR_CHUNK_ROUNDS * NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x < a.T) thr[threadIdx.x] = a.state[threadIdx.x].prefix;
-    __syncthreads();
+    const int t = blockIdx.y;
+    if (a.k[t] <= 0) return;
+    const uint64_t th = a.state[t].prefix;
     const int64_t base = (int64_t)blockIdx.x * PR_CHUNK;
-    uint64_t ck[PR_CHUNK_ROUNDS];
+    uint64_t m[PR_CHUNK_ROUNDS];
 #pragma unroll
     for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
         int64_t i = base + r * PR_CHUNK_THREADS + threadIdx.x;
-        ck[r] = i < a.n ? comp_key(a.imp, i) : ~0ull;
+        const uint64_t ck = i < a.n ? comp_key(a.imp, i) : ~0ull;
+        m[r] = __ballot(ck <= th);
     }
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) off[r * NW + wave] = (uint32_t)__popcll(m[r]);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const uint32_t v = off[lane];
+        uint32_t incl = v;
+#pragma unroll
+        for (int o = 1; o < MGS_WAVE; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, o, MGS_WAVE);
+            if (lane >= o) incl += y;
+        }
+        off[lane] = a.cnt[(int64_t)t * a.nblk + blockIdx.x] + incl - v;
+    }
+    __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int t = 0; t < a.T; ++t) {
-        if (a.k[t] <= 0) continue;  // uniform
-        const uint64_t th = thr[t];
+    int32_t* out = a.kept + a.koff[t];
 #pragma unroll
-        for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
-            uint64_t m = __ballot(ck[r] <= th);
-            if (lane == 0) off[r][wave] = (uint32_t)__popcll(m);
+    for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
+        if ((m[r] >> lane) & 1ull) {
+            const uint32_t pos = off[r * NW + wave] + (uint32_t)__popcll(m[r] & lt_mask);
+            if (pos < (uint64_t)a.k[t]) out[pos] = (int32_t)(base + r * PR_CHUNK_THREADS + threadIdx.x);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t s = a.cnt[(int64_t)t * a.nblk + blockIdx.x];
-            for (int r = 0; r < PR_CHUNK_ROUNDS; ++r)
-                for (int w = 0; w < NW; ++w) {
-                    uint32_t v = off[r][w];
-                    off[r][w] = s;
-                    s += v;
-                }
-        }
-        __syncthreads();
-        int32_t* out = a.kept + a.koff[t];
-#pragma unroll
-        for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
-            bool keep = ck[r] <= th;
-            uint64_t m = __ballot(keep);
-            const uint32_t pos = off[r][wave] + (uint32_t)__popcll(m & lt_mask);
-            if (keep && pos < (uint64_t)a.k[t]) out[pos] = (int32_t)(ck[r] & 0xffffffffu);
-        }
-        __syncthreads();
     }
 }
 
@@ -360,8 +372,8 @@ extern "C" int mgs_prune_select(const float* d_imp, int64_t n, const int64_t* h_
                            level);
         hipLaunchKernelGGL(prune_select_kernel, dim3(T), dim3(256), 0, s, a, level);
     }
-    hipLaunchKernelGGL(prune_count_kernel, dim3((unsigned)a.nblk), dim3(PR_CHUNK_THREADS), 0, s, a);
+    hipLaunchKernelGGL(prune_count_kernel, dim3((unsigned)a.nblk, (unsigned)T), dim3(PR_CHUNK_THREADS), 0, s, a);
     hipLaunchKernelGGL(prune_scan_kernel, dim3(T), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(prune_write_kernel, dim3((unsigned)a.nblk), dim3(PR_CHUNK_THREADS), 0, s, a);
+    hipLaunchKernelGGL(prune_write_kernel, dim3((unsigned)a.nblk, (unsigned)T), dim3(PR_CHUNK_THREADS), 0, s, a);
     return mgs_last_launch();
 }

@@ -4,8 +4,10 @@
 // Encoding" (those bounds are part of the metadata).
 //
 // Both kernels are HBM-bound: one workgroup per (channel, group) reads the
-// group's values once for the minimum / maximum and once more (from L2) for
-// the codes; the dequantizer reads 2-byte codes and writes FP32 values.  The
+// group's values once for the minimum / maximum and keeps them in registers
+// for the codes (groups beyond 8192 elements (1024 threads) or 2048 (256
+// threads) read them again, from L2); the dequantizer reads 2-byte codes and
+// writes FP32 values.  The
 // quantizer expression is the literal FP32 definition, so codes equal those
 // of the sweep bit for bit.
 #include <algorithm>
@@ -15,10 +17,16 @@
 namespace mgs {
 namespace {
 
-constexpr int QT = 256;
+constexpr int QU = 8;  // elements per thread and batch: independent loads in flight
 
 __device__ __forceinline__ int clamp_bits(uint8_t b) { return b < 1 ? 1 : (b > 16 ? 16 : b); }
 
+// One workgroup of QT threads per (channel, group), groups strided over the
+// grid.  A batch is QT * QU consecutive elements of the group: every thread
+// first issues its QU index loads, then its QU value loads, so that each
+// thread has QU gathers in flight instead of one.  Groups of up to QT * QU
+// elements stay in registers between the minimum / maximum and the codes.
+template <int QT>
 __global__ __launch_bounds__(QT) void quantize_kernel(const float* __restrict__ attr, int64_t ld,
                                                       int C, const int32_t* __restrict__ kept,
                                                       int64_t k, int G, int64_t ng,
@@ -26,8 +34,10 @@ __global__ __launch_bounds__(QT) void quantize_kernel(const float* __restrict__ 
                                                       uint16_t* __restrict__ codes,
                                                       float* __restrict__ gmin,
                                                       float* __restrict__ gmax) {
+    constexpr int CAP = QT * QU;
     __shared__ float smn[QT / MGS_WAVE], smx[QT / MGS_WAVE];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     for (int64_t blk = blockIdx.x; blk < (int64_t)C * ng; blk += gridDim.x) {
         const int c = (int)(blk / ng);
         const int64_t g = blk - (int64_t)c * ng;
@@ -35,11 +45,29 @@ __global__ __launch_bounds__(QT) void quantize_kernel(const float* __restrict__ 
         const int n = (int)std::min<int64_t>(G, k - j0);
         const float* row = attr + (int64_t)c * ld;
         const int32_t* J = kept + j0;
+        float xr[QU];
+        auto load = [&](int b0) {
+            int32_t id[QU];
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int j = b0 + u * QT + tid;
+                id[u] = j < n ? J[j] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int j = b0 + u * QT + tid;
+                xr[u] = j < n ? row[id[u]] : 0.0f;
+            }
+        };
         float mn = INFINITY, mx = -INFINITY;
-        for (int j = threadIdx.x; j < n; j += QT) {
-            float x = row[J[j]];
-            mn = fminf(mn, x);
-            mx = fmaxf(mx, x);
+        for (int b0 = 0; b0 < n; b0 += CAP) {
+            load(b0);
+#pragma unroll
+            for (int u = 0; u < QU; ++u)
+                if (b0 + u * QT + tid < n) {
+                    mn = fminf(mn, xr[u]);
+                    mx = fmaxf(mx, xr[u]);
+                }
         }
         mn = wave_min_f32(mn);
         mx = wave_max_f32(mx);
@@ -64,33 +92,42 @@ __global__ __launch_bounds__(QT) void quantize_kernel(const float* __restrict__ 
             float r = mx / S;
             Z = __builtin_rintf(P - r);
         }
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             gmin[blk] = mn;
             gmax[blk] = mx;
         }
         uint16_t* out = codes + (int64_t)c * k + j0;
         const float qmax = P - 1.0f;
-        for (int j = threadIdx.x; j < n; j += QT) {
-            uint16_t q = 0;
-            if (S != 0.0f) {
-                float x = row[J[j]];
-                float t = x / S;
-                t = t + Z;
-                t = __builtin_amdgcn_fmed3f(t, 0.0f, qmax);
-                q = (uint16_t)__builtin_rintf(t);
+        for (int b0 = 0; b0 < n; b0 += CAP) {
+            if (n > CAP) load(b0);  // otherwise the group is still in registers
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int j = b0 + u * QT + tid;
+                if (j < n) {
+                    uint16_t q = 0;
+                    if (S != 0.0f) {
+                        float t = xr[u] / S;
+                        t = t + Z;
+                        t = __builtin_amdgcn_fmed3f(t, 0.0f, qmax);
+                        q = (uint16_t)__builtin_rintf(t);
+                    }
+                    out[j] = q;
+                }
             }
-            out[j] = q;
         }
-        __syncthreads();
+        __syncthreads();  // smn / smx are reused by the next group
     }
 }
 
+template <int QT>
 __global__ __launch_bounds__(QT) void dequantize_kernel(const uint16_t* __restrict__ codes,
                                                         int64_t k, int C, int G, int64_t ng,
                                                         const uint8_t* __restrict__ bw,
                                                         const float* __restrict__ gmin,
                                                         const float* __restrict__ gmax,
                                                         float* __restrict__ out) {
+    constexpr int CAP = QT * QU;
+    const int tid = threadIdx.x;
     for (int64_t blk = blockIdx.x; blk < (int64_t)C * ng; blk += gridDim.x) {
         const int c = (int)(blk / ng);
         const int64_t g = blk - (int64_t)c * ng;
@@ -108,13 +145,25 @@ __global__ __launch_bounds__(QT) void dequantize_kernel(const uint16_t* __restri
         }
         const uint16_t* q = codes + (int64_t)c * k + j0;
         float* o = out + (int64_t)c * k + j0;
-        for (int j = threadIdx.x; j < n; j += QT) {
-            float v = mn;
-            if (S != 0.0f) {
-                float d = (float)q[j] - Z;
-                v = d * S;
+        for (int b0 = 0; b0 < n; b0 += CAP) {
+            uint16_t qv[QU];
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int j = b0 + u * QT + tid;
+                qv[u] = j < n ? q[j] : (uint16_t)0;
             }
-            o[j] = v;
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int j = b0 + u * QT + tid;
+                if (j < n) {
+                    float v = mn;
+                    if (S != 0.0f) {
+                        float d = (float)qv[u] - Z;
+                        v = d * S;
+                    }
+                    o[j] = v;
+                }
+            }
         }
     }
 }
@@ -130,9 +179,15 @@ extern "C" int mgs_quantize(const float* d_attr, int64_t ld, int32_t C, const in
     if (!d_attr || !d_kept || !d_bw || !d_codes || !d_gmin || !d_gmax) return MGS_EINVAL;
     const int64_t ng = (k + G - 1) / G;
     const int64_t blocks = std::min<int64_t>((int64_t)C * ng, 1 << 20);
-    hipLaunchKernelGGL(mgs::quantize_kernel, dim3((unsigned)blocks), dim3(mgs::QT), 0,
-                       (hipStream_t)stream, d_attr, ld, C, d_kept, k, G, ng, d_bw, d_codes, d_gmin,
-                       d_gmax);
+    // large groups: 1024 threads per group; small ones: 256
+    if (G >= 4096)
+        hipLaunchKernelGGL(mgs::quantize_kernel<1024>, dim3((unsigned)blocks), dim3(1024), 0,
+                           (hipStream_t)stream, d_attr, ld, C, d_kept, k, G, ng, d_bw, d_codes, d_gmin,
+                           d_gmax);
+    else
+        hipLaunchKernelGGL(mgs::quantize_kernel<256>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, d_attr, ld, C, d_kept, k, G, ng, d_bw, d_codes, d_gmin,
+                           d_gmax);
     return mgs_last_launch();
 }
 
@@ -144,7 +199,11 @@ extern "C" int mgs_dequantize(const uint16_t* d_codes, int64_t k, int32_t C, int
     if (!d_codes || !d_bw || !d_gmin || !d_gmax || !d_out) return MGS_EINVAL;
     const int64_t ng = (k + G - 1) / G;
     const int64_t blocks = std::min<int64_t>((int64_t)C * ng, 1 << 20);
-    hipLaunchKernelGGL(mgs::dequantize_kernel, dim3((unsigned)blocks), dim3(mgs::QT), 0,
-                       (hipStream_t)stream, d_codes, k, C, G, ng, d_bw, d_gmin, d_gmax, d_out);
+    if (G >= 4096)
+        hipLaunchKernelGGL(mgs::dequantize_kernel<1024>, dim3((unsigned)blocks), dim3(1024), 0,
+                           (hipStream_t)stream, d_codes, k, C, G, ng, d_bw, d_gmin, d_gmax, d_out);
+    else
+        hipLaunchKernelGGL(mgs::dequantize_kernel<256>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, d_codes, k, C, G, ng, d_bw, d_gmin, d_gmax, d_out);
     return mgs_last_launch();
 }
