@@ -17,8 +17,9 @@
 // bucket is resolved there (every lower threshold bit set), and a pass with
 // no unresolved k exits at once: without ties across the k-th key the index
 // digits cost nothing.  A compaction then writes each kept set in index
-// order: per-(chunk, k) counts, a per-k scan over chunks, and a write pass
-// per (chunk, k) that ranks kept elements with wavefront ballots.
+// order: per-chunk counts, a per-k scan over chunks, and a write pass that
+// ranks kept elements with wavefront ballots; a block of the counting and
+// writing passes takes one chunk and a group of k, sized for ~2048 blocks.
 #include <algorithm>
 #include <cstring>
 
@@ -195,27 +196,33 @@ __global__ __launch_bounds__(256) void prune_select_kernel(PruneArgs a, int leve
     }
 }
 
-// Compaction, phase counts: kept keys of one k (blockIdx.y) in one chunk.
-__global__ __launch_bounds__(PR_CHUNK_THREADS) void prune_count_kernel(PruneArgs a) {
+// Compaction, phase counts: kept keys of ratios [blockIdx.y * tb, + tb) in
+// one chunk (the chunk's keys are read once for the tb ratios).
+__global__ __launch_bounds__(PR_CHUNK_THREADS) void prune_count_kernel(PruneArgs a, int tb) {
     __shared__ uint32_t wsum[PR_CHUNK_THREADS / MGS_WAVE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int t = blockIdx.y;
-    if (a.k[t] <= 0) return;  // its counts are never read
-    const uint64_t th = a.state[t].prefix;
     const int64_t base = (int64_t)blockIdx.x * PR_CHUNK;
-    uint32_t c = 0;
+    uint64_t ck[PR_CHUNK_ROUNDS];
 #pragma unroll
     for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
         int64_t i = base + r * PR_CHUNK_THREADS + threadIdx.x;
-        const uint64_t ck = i < a.n ? comp_key(a.imp, i) : ~0ull;
-        c += (uint32_t)__popcll(__ballot(ck <= th));
+        ck[r] = i < a.n ? comp_key(a.imp, i) : ~0ull;
     }
-    if (lane == 0) wsum[wave] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < PR_CHUNK_THREADS / MGS_WAVE; ++w) s += wsum[w];
-        a.cnt[(int64_t)t * a.nblk + blockIdx.x] = s;
+    const int t1 = min(a.T, (int)(blockIdx.y + 1) * tb);
+    for (int t = blockIdx.y * tb; t < t1; ++t) {
+        if (a.k[t] <= 0) continue;  // uniform; its counts are never read
+        const uint64_t th = a.state[t].prefix;
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) c += (uint32_t)__popcll(__ballot(ck[r] <= th));
+        if (lane == 0) wsum[wave] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t sum = 0;
+            for (int w = 0; w < PR_CHUNK_THREADS / MGS_WAVE; ++w) sum += wsum[w];
+            a.cnt[(int64_t)t * a.nblk + blockIdx.x] = sum;
+        }
+        __syncthreads();
     }
 }
 
@@ -245,50 +252,55 @@ __global__ __launch_bounds__(1024) void prune_scan_kernel(PruneArgs a) {
     }
 }
 
-// Compaction, phase write, one block per (chunk, k): each kept key's position
-// is the chunk's offset, plus the kept keys of earlier (round, wave) pairs
-// (an exclusive scan of the 64 ballot counts by one wavefront), plus the
-// lanes below.
-__global__ __launch_bounds__(PR_CHUNK_THREADS) void prune_write_kernel(PruneArgs a) {
+// Compaction, phase write, one block per (chunk, group of tb ratios): each
+// kept key's position is the chunk's offset, plus the kept keys of earlier
+// (round, wave) pairs (an exclusive scan of the 64 ballot counts by one
+// wavefront), plus the lanes below.
+__global__ __launch_bounds__(PR_CHUNK_THREADS) void prune_write_kernel(PruneArgs a, int tb) {
     constexpr int NW = PR_CHUNK_THREADS / MGS_WAVE;
     static_assert(PR_CHUNK_ROUNDS * NW == MGS_WAVE, "one count per lane of the scanning wavefront");
     __shared__ uint32_t off[PR_CHUNK_ROUNDS * NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int t = blockIdx.y;
-    if (a.k[t] <= 0) return;
-    const uint64_t th = a.state[t].prefix;
     const int64_t base = (int64_t)blockIdx.x * PR_CHUNK;
-    uint64_t m[PR_CHUNK_ROUNDS];
+    uint64_t ck[PR_CHUNK_ROUNDS];
 #pragma unroll
     for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
         int64_t i = base + r * PR_CHUNK_THREADS + threadIdx.x;
-        const uint64_t ck = i < a.n ? comp_key(a.imp, i) : ~0ull;
-        m[r] = __ballot(ck <= th);
+        ck[r] = i < a.n ? comp_key(a.imp, i) : ~0ull;
     }
-    if (lane == 0) {
-#pragma unroll
-        for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) off[r * NW + wave] = (uint32_t)__popcll(m[r]);
-    }
-    __syncthreads();
-    if (wave == 0) {
-        const uint32_t v = off[lane];
-        uint32_t incl = v;
-#pragma unroll
-        for (int o = 1; o < MGS_WAVE; o <<= 1) {
-            const uint32_t y = (uint32_t)__shfl_up((int)incl, o, MGS_WAVE);
-            if (lane >= o) incl += y;
-        }
-        off[lane] = a.cnt[(int64_t)t * a.nblk + blockIdx.x] + incl - v;
-    }
-    __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int32_t* out = a.kept + a.koff[t];
+    const int t1 = min(a.T, (int)(blockIdx.y + 1) * tb);
+    for (int t = blockIdx.y * tb; t < t1; ++t) {
+        if (a.k[t] <= 0) continue;  // uniform
+        const uint64_t th = a.state[t].prefix;
+        uint64_t m[PR_CHUNK_ROUNDS];
 #pragma unroll
-    for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
-        if ((m[r] >> lane) & 1ull) {
-            const uint32_t pos = off[r * NW + wave] + (uint32_t)__popcll(m[r] & lt_mask);
-            if (pos < (uint64_t)a.k[t]) out[pos] = (int32_t)(base + r * PR_CHUNK_THREADS + threadIdx.x);
+        for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) m[r] = __ballot(ck[r] <= th);
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) off[r * NW + wave] = (uint32_t)__popcll(m[r]);
         }
+        __syncthreads();
+        if (wave == 0) {
+            const uint32_t v = off[lane];
+            uint32_t incl = v;
+#pragma unroll
+            for (int o = 1; o < MGS_WAVE; o <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_up((int)incl, o, MGS_WAVE);
+                if (lane >= o) incl += y;
+            }
+            off[lane] = a.cnt[(int64_t)t * a.nblk + blockIdx.x] + incl - v;
+        }
+        __syncthreads();
+        int32_t* out = a.kept + a.koff[t];
+#pragma unroll
+        for (int r = 0; r < PR_CHUNK_ROUNDS; ++r) {
+            if ((m[r] >> lane) & 1ull) {
+                const uint32_t pos = off[r * NW + wave] + (uint32_t)__popcll(m[r] & lt_mask);
+                if (pos < (uint64_t)a.k[t]) out[pos] = (int32_t)(base + r * PR_CHUNK_THREADS + threadIdx.x);
+            }
+        }
+        __syncthreads();  // off is rewritten for the next ratio
     }
 }
 
@@ -372,8 +384,12 @@ extern "C" int mgs_prune_select(const float* d_imp, int64_t n, const int64_t* h_
                            level);
         hipLaunchKernelGGL(prune_select_kernel, dim3(T), dim3(256), 0, s, a, level);
     }
-    hipLaunchKernelGGL(prune_count_kernel, dim3((unsigned)a.nblk, (unsigned)T), dim3(PR_CHUNK_THREADS), 0, s, a);
+    // ratios per compaction block: about 2048 blocks in all (enough to fill
+    // the chip; more blocks would only read the same keys again)
+    const int tb = (int)std::min<int64_t>(T, std::max<int64_t>(1, (T * a.nblk + 2047) / 2048));
+    const unsigned tgroups = (unsigned)((T + tb - 1) / tb);
+    hipLaunchKernelGGL(prune_count_kernel, dim3((unsigned)a.nblk, tgroups), dim3(PR_CHUNK_THREADS), 0, s, a, tb);
     hipLaunchKernelGGL(prune_scan_kernel, dim3(T), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(prune_write_kernel, dim3((unsigned)a.nblk, (unsigned)T), dim3(PR_CHUNK_THREADS), 0, s, a);
+    hipLaunchKernelGGL(prune_write_kernel, dim3((unsigned)a.nblk, tgroups), dim3(PR_CHUNK_THREADS), 0, s, a, tb);
     return mgs_last_launch();
 }
