@@ -356,6 +356,21 @@ def test_prune_large_workload(torch, orc):
     np.testing.assert_array_equal(got, orc.prune_select(imp, k))
 
 
+@pytest.mark.parametrize("ties", [False, True])
+def test_prune_max_ratios(torch, orc, ties):
+    """64 keep counts (the maximum) over 2x10^5 keys: the compaction blocks then
+    take two ratios each; unsorted and repeated counts, 0 and n included."""
+    rng = np.random.default_rng(21 + int(ties))
+    n = 200_000
+    imp = rng.lognormal(0, 2, n).astype(np.float32)
+    if ties:
+        imp = np.round(imp * 4).astype(np.float32)
+    k = rng.integers(0, n + 1, 64).astype(np.int64)
+    k[:4] = [0, n, 1, k[5]]
+    got = host(mgs.prune_select(dev(torch, imp), k))
+    np.testing.assert_array_equal(got, orc.prune_select(imp, k))
+
+
 def test_prune_nonfinite(torch):
     imp = np.ones(1000, np.float32)
     imp[5] = np.inf
