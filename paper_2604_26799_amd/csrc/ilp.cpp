@@ -42,10 +42,15 @@ namespace {
 
 constexpr double kInf = std::numeric_limits<double>::infinity();
 constexpr size_t kStateCap = 20u * 1000u * 1000u;
-// Incumbent passes (beam width, first core size), tried in order: a cheap
-// schedule first; a wider one only when the exact pass of the cheaper one
-// exceeds the state limit (its weaker incumbent left too large a gap).
-constexpr struct { size_t beam, k0; } kSchedules[] = {{1000, 32}, {4000, 128}, {16000, 128}};
+// Incumbent passes (beam width, first core size, largest exact core), tried
+// in order: a cheap schedule first; a wider one when the exact pass of the
+// cheaper one exceeds the state limit, or would span more classes than the
+// schedule's exact core (its weaker incumbent left too large a gap: a wider
+// beam over a small core usually closes most of it for a fraction of what
+// such an exact pass costs).
+constexpr size_t kNoLimit = std::numeric_limits<size_t>::max();
+constexpr struct { size_t beam, k0, exact_max; } kSchedules[] = {
+    {1000, 32, 400}, {4000, 128, 1600}, {16000, 128, kNoLimit}};
 
 struct Opt {
     double e;
@@ -578,7 +583,7 @@ struct Mckp {
         } else {
             int rc = MGS_ELIMIT;
             for (const auto& sc : kSchedules) {
-                rc = expand(choice, sc.beam, sc.k0);
+                rc = expand(choice, sc.beam, sc.k0, sc.exact_max);
                 if (rc != MGS_ELIMIT) break;
             }
             if (rc) return rc;
@@ -594,7 +599,7 @@ struct Mckp {
         return MGS_OK;
     }
 
-    int expand(uint8_t* choice, size_t beam, size_t k0) {
+    int expand(uint8_t* choice, size_t beam, size_t k0, size_t exact_max) {
     // ---- 4. expanding core: DP over the classes whose alternatives are
     // cheapest in reduced cost improves the incumbent, which shrinks the gap;
     // once every class that can still change (rcmin <= gap) fits in the core,
@@ -608,6 +613,7 @@ struct Mckp {
             need.push_back(c);
         }
         const bool final_pass = need.size() <= K;
+        if (final_pass && need.size() > exact_max) return MGS_ELIMIT;  // the next schedule first
         std::vector<int64_t> core = final_pass ? need : std::vector<int64_t>(order.begin(), order.begin() + K);
         if (final_pass) std::sort(core.begin(), core.end());  // index order for the tie rule
         std::vector<char> in_core(ncls, 0);
