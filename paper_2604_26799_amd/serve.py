@@ -130,7 +130,7 @@ class Server:
 
     def __init__(self, store: SceneStore, G: int = 8192, bits=range(2, 17), mode: str = "batched",
                  mem_cap_bytes: int = 32 << 30, host_workers: int = 4, ilp_threads: int = 0,
-                 keep_codes: bool = False, max_batch: int = mgs.MAX_JOBS):
+                 keep_codes: bool = False, max_batch: int = mgs.MAX_JOBS, warm_up: bool = True):
         import torch
         assert mode in ("batched", "plain")
         self.torch = torch
@@ -164,6 +164,29 @@ class Server:
         self.ws_ring = [mgs.workspace(need, self.dev) for _ in range(8)]
         self.ws_next = 0
         self.plain_ws = mgs.workspace(1 << 22, self.dev)
+        if warm_up:
+            self._warm_up()
+
+    def _warm_up(self):
+        """One small job through every stage before the stream starts: the first
+        use of each kernel loads its code object and the first pinned and device
+        allocations of each size are slow, which would otherwise land on the
+        first jobs' latency.  Nothing of it is kept or counted."""
+        n = min(50_000, self.store.n)
+        job = synth.Job(-1, 0.0, n, n * 80 // 30, 0, list(synth.job_stream(1)[0].ratios))
+        k = synth.keep_counts(job.n, job.ratios)
+        live = _Live(job, k, 0, 0.0)
+        self._admit(live)
+        self._launch_sweep([live])
+        live.ev.synchronize()
+        live.res = self._solve(live)
+        self._launch_codes(live)
+        if live.ev is not None:
+            live.ev.synchronize()
+        live.dev.clear()
+        live.host.clear()
+        self.launches = 0
+        self.batch_sizes.clear()
 
     # ---- per-job device work -------------------------------------------------
     def _admit(self, live: _Live):
