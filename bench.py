@@ -97,8 +97,8 @@ def committed_traffic(workload: str, shape):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the sweep's (ratio, channel, group) tiles would shard across "
-              "GPUs, but runs on more than one GPU are not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU only: the sweep's (ratio, channel, group) tiles would shard "
+              "across GPUs, but only the single-GPU path is implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
