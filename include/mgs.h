@@ -207,7 +207,8 @@ int mgs_dequantize(const uint16_t* d_codes, int64_t k, int32_t C, int32_t G, con
  * distance of the winner.  d_nfallback (optional, device int64) receives
  * the number of rows that needed the exact full scan.  Exact: the result
  * equals the FP64 definition bit for bit.
- * Limits: 1 <= D <= MGS_MAX_VQ_DIM, 1 <= K < 2^31, N >= 0.
+ * Limits: 1 <= D <= MGS_MAX_VQ_DIM, 1 <= K <= 2^30, 0 <= N < 2^31
+ * (mgs_vq_assign_ws_bytes returns 0 outside them).
  * Errors: MGS_EINVAL, MGS_EWORKSPACE; non-finite data -> MGS_ENONFINITE in
  * the status word.
  * ====================================================================== */
@@ -233,7 +234,7 @@ int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float* d_cb, int
  * rows keep their value).  The FP64 sums are atomic, so the mean is
  * reproducible to about B * 2^-53 relative before the FP32 rounding.
  * Workspace: mgs_kmeans_step_ws_bytes(B, D, K).  Errors: MGS_EINVAL
- * (N < 0, B outside [0, 2^31), D outside [1, MGS_MAX_VQ_DIM], K < 1, NULL
+ * (N < 0, B outside [0, 2^31), D outside [1, MGS_MAX_VQ_DIM], K outside [1, 2^30], NULL
  * pointers), MGS_EWORKSPACE; non-finite rows or centers, and batch indices
  * outside [0, N) (gathered as zero rows), raise MGS_ENONFINITE in the
  * status word.

@@ -122,7 +122,7 @@ unsigned km_blocks(int64_t n) {
 }  // namespace mgs
 
 extern "C" size_t mgs_kmeans_step_ws_bytes(int64_t B, int32_t D, int32_t K) {
-    if (B < 0 || D < 1 || D > MGS_MAX_VQ_DIM || K < 1) return 0;
+    if (B < 0 || D < 1 || D > MGS_MAX_VQ_DIM || K < 1 || K > (1 << 30)) return 0;
     return mgs::km_layout(B, D, K).total;
 }
 
@@ -130,7 +130,8 @@ extern "C" int mgs_kmeans_step(const float* d_x, int64_t N, int32_t D, const int
                                float* d_cb, int32_t K, int64_t* d_counts, int32_t* d_assign, void* d_ws,
                                size_t ws_bytes, void* stream) {
     using namespace mgs;
-    if (N < 0 || B < 0 || B >= ((int64_t)1 << 31) || D < 1 || D > MGS_MAX_VQ_DIM || K < 1 || !d_cb ||
+    if (N < 0 || B < 0 || B >= ((int64_t)1 << 31) || D < 1 || D > MGS_MAX_VQ_DIM || K < 1 || K > (1 << 30) ||
+        !d_cb ||
         !d_counts)
         return MGS_EINVAL;
     if (B > 0 && (!d_x || !d_batch)) return MGS_EINVAL;

@@ -464,7 +464,7 @@ VqLayout vq_layout(int64_t N, int D, int K) {
 }  // namespace mgs
 
 extern "C" size_t mgs_vq_assign_ws_bytes(int64_t N, int32_t D, int32_t K) {
-    if (N < 0 || D < 1 || D > MGS_MAX_VQ_DIM || K < 1) return 0;
+    if (N < 0 || D < 1 || D > MGS_MAX_VQ_DIM || K < 1 || K > (1 << 30)) return 0;
     return mgs::vq_layout(N, D, K).total;
 }
 
@@ -472,7 +472,7 @@ extern "C" int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float
                              int32_t* d_idx, double* d_dist, int64_t* d_nfallback, void* d_ws,
                              size_t ws_bytes, void* stream) {
     using namespace mgs;
-    if (N < 0 || N >= ((int64_t)1 << 31) || D < 1 || D > MGS_MAX_VQ_DIM || K < 1 || !d_cb)
+    if (N < 0 || N >= ((int64_t)1 << 31) || D < 1 || D > MGS_MAX_VQ_DIM || K < 1 || K > (1 << 30) || !d_cb)
         return MGS_EINVAL;
     if (N > 0 && (!d_x || !d_idx)) return MGS_EINVAL;
     VqLayout L = vq_layout(N, D, K);

@@ -145,6 +145,8 @@ def test_other_entry_points_reject_bad_arguments():
     assert L.mgs_vq_assign(fake, 10, 0, fake, 4, fake, None, None, fake, 1 << 20, None) == mgs.EINVAL
     assert L.mgs_vq_assign(fake, 10, 65, fake, 4, fake, None, None, fake, 1 << 20, None) == mgs.EINVAL
     assert L.mgs_vq_assign(fake, 10, 36, fake, 0, fake, None, None, fake, 1 << 20, None) == mgs.EINVAL
+    assert L.mgs_vq_assign(fake, 10, 36, fake, (1 << 30) + 1, fake, None, None, fake, 1 << 20, None) == mgs.EINVAL
+    assert L.mgs_vq_assign_ws_bytes(10, 36, (1 << 30) + 1) == 0
     assert L.mgs_vq_assign(fake, 10, 36, fake, 4, fake, None, None, None, 0, None) == mgs.EWORKSPACE
     assert L.mgs_status_fetch(None, None) == mgs.EWORKSPACE
 
