@@ -22,7 +22,9 @@
 // Each step is three launches over the live-node list: pair flags and block
 // sums, a one-block scan of the block sums (which also advances the live and
 // AC counts kept on the device), and the merges with the compaction of the
-// list.  Nothing is read back to the host between steps.
+// list.  Nothing is read back to the host between steps.  Consecutive lanes
+// take consecutive live nodes, so the list, the codes and (while the live
+// slots are dense) the values are read coalesced.
 #include <cstring>
 
 #include "common.h"
@@ -129,9 +131,9 @@ __global__ __launch_bounds__(RH_THREADS) void raht_count_kernel(RahtArgs a, int 
     const int32_t* live = a.live[s & 1];
     const int64_t n = a.n_live[s];
     int64_t v = 0;
-    const int64_t i0 = (int64_t)blockIdx.x * RH_SPAN + (int64_t)threadIdx.x * RH_ITEMS;
+    const int64_t i0 = (int64_t)blockIdx.x * RH_SPAN + threadIdx.x;
     for (int e = 0; e < RH_ITEMS; ++e) {
-        const int64_t i = i0 + e;
+        const int64_t i = i0 + (int64_t)e * RH_THREADS;
         if (i >= n) break;
         const PairFlags f = pair_flags(a, live, n, i, s);
         v += (int64_t)f.first + ((int64_t)(!f.second) << 32);
@@ -164,27 +166,54 @@ __global__ __launch_bounds__(RH_THREADS) void raht_scan_kernel(RahtArgs a, int s
     }
 }
 
+// The block's live nodes are taken in rounds of RH_THREADS consecutive ones
+// (consecutive lanes, consecutive nodes: coalesced reads of the list, the
+// codes and the values); a node's output positions follow node order, from
+// wavefront ballots: per (round, wave) counts, one wavefront's exclusive scan
+// of them, plus the lanes below.
 __global__ __launch_bounds__(RH_THREADS) void raht_merge_kernel(RahtArgs a, int s) {
+    constexpr int NW = RH_THREADS / MGS_WAVE;
+    static_assert(RH_ITEMS * NW <= MGS_WAVE, "one (round, wave) count per lane of the scanning wavefront");
+    __shared__ int64_t off[RH_ITEMS * NW];
     const int32_t* live = a.live[s & 1];
     int32_t* next = a.live[(s + 1) & 1];
     const int64_t n = a.n_live[s];
-    const int64_t i0 = (int64_t)blockIdx.x * RH_SPAN + (int64_t)threadIdx.x * RH_ITEMS;
-    PairFlags f[RH_ITEMS];
-    int64_t v = 0;
+    const int lane = threadIdx.x & (MGS_WAVE - 1), wave = threadIdx.x / MGS_WAVE;
+    const int64_t i0 = (int64_t)blockIdx.x * RH_SPAN + threadIdx.x;
+    uint64_t mf[RH_ITEMS], mk[RH_ITEMS];
+#pragma unroll
     for (int e = 0; e < RH_ITEMS; ++e) {
-        const int64_t i = i0 + e;
-        f[e] = i < n ? pair_flags(a, live, n, i, s) : PairFlags{false, true};
-        if (i < n) v += (int64_t)f[e].first + ((int64_t)(!f[e].second) << 32);
+        const int64_t i = i0 + (int64_t)e * RH_THREADS;
+        const PairFlags f = i < n ? pair_flags(a, live, n, i, s) : PairFlags{false, true};
+        mf[e] = __ballot(f.first);
+        mk[e] = __ballot(!f.second);
     }
-    int64_t total = 0;
-    int64_t off = block_exscan_i64(v, total) + a.bsum[blockIdx.x];
-    int64_t pos_pair = a.ac_base[s] + (off & 0xFFFFFFFFll);
-    int64_t pos_keep = off >> 32;
+    if (lane == 0) {
+#pragma unroll
+        for (int e = 0; e < RH_ITEMS; ++e)
+            off[e * NW + wave] = (int64_t)__popcll(mf[e]) + ((int64_t)__popcll(mk[e]) << 32);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const int64_t v = lane < RH_ITEMS * NW ? off[lane] : 0;
+        int64_t incl = v;
+#pragma unroll
+        for (int o = 1; o < MGS_WAVE; o <<= 1) {
+            const int64_t y = __shfl_up(incl, o, MGS_WAVE);
+            if (lane >= o) incl += y;
+        }
+        if (lane < RH_ITEMS * NW) off[lane] = a.bsum[blockIdx.x] + incl - v;
+    }
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int e = 0; e < RH_ITEMS; ++e) {
-        const int64_t i = i0 + e;
-        if (i >= n) break;
+        const int64_t i = i0 + (int64_t)e * RH_THREADS;
+        if (i >= n) continue;
+        const int64_t o = off[e * NW + wave];
         const int32_t sa = live[i];
-        if (f[e].first) {
+        if ((mf[e] >> lane) & 1ull) {
+            const int64_t pos_pair = a.ac_base[s] + (o & 0xFFFFFFFFll) + __popcll(mf[e] & lt);
             const int32_t sb = live[i + 1];
             const int64_t w1 = a.w[sa], w2 = a.w[sb];
             a.pa[pos_pair] = sa;
@@ -193,6 +222,7 @@ __global__ __launch_bounds__(RH_THREADS) void raht_merge_kernel(RahtArgs a, int 
             a.wb[pos_pair] = w2;
             if (a.values) {
                 const double s1 = sqrt((double)w1), s2 = sqrt((double)w2), sw = sqrt((double)(w1 + w2));
+#pragma unroll 4
                 for (int k = 0; k < a.C; ++k) {
                     const double a1 = a.val[(int64_t)k * a.N + sa], a2 = a.val[(int64_t)k * a.N + sb];
                     const double L = (s1 * a1 + s2 * a2) / sw;
@@ -202,9 +232,8 @@ __global__ __launch_bounds__(RH_THREADS) void raht_merge_kernel(RahtArgs a, int 
                 }
             }
             a.w[sa] = w1 + w2;
-            ++pos_pair;
         }
-        if (!f[e].second) next[pos_keep++] = sa;
+        if ((mk[e] >> lane) & 1ull) next[(o >> 32) + __popcll(mk[e] & lt)] = sa;
     }
 }
 
@@ -228,6 +257,7 @@ __global__ void raht_unmerge_kernel(RahtArgs a, int s) {
         const int32_t sa = a.pa[p], sb = a.pb[p];
         const int64_t w1 = a.wa[p], w2 = a.wb[p];
         const double s1 = sqrt((double)w1), s2 = sqrt((double)w2), sw = sqrt((double)(w1 + w2));
+#pragma unroll 4
         for (int k = 0; k < a.C; ++k) {
             const double L = a.val[(int64_t)k * a.N + sa];
             const double H = (double)a.coef_in[(int64_t)k * a.ld + 1 + p];
