@@ -11,20 +11,29 @@
 // with bit s clear (weight w1, value a1) and the one with it set (w2, a2):
 //   L = (sqrt(w1) a1 + sqrt(w2) a2) / sqrt(w1 + w2)      (goes up, weight w1 + w2)
 //   H = (sqrt(w1) a2 - sqrt(w2) a1) / sqrt(w1 + w2)      (AC coefficient)
-// A merged node keeps the slot of its first node, so live nodes stay in
-// Morton order.  Output per channel: coefficient 0 = DC (the root's value),
-// then the AC coefficients in the order they are made (step by step, within
-// a step in Morton order).  FP64 arithmetic in exactly the order above, FP32
-// storage.  The inverse recomputes the merges from the positions and undoes
-// them in reverse:  a1 = (sqrt(w1) L - sqrt(w2) H) / sqrt(w1 + w2),
-//                   a2 = (sqrt(w2) L + sqrt(w1) H) / sqrt(w1 + w2).
+// A merged node keeps the slot of its first leaf.  Output per channel:
+// coefficient 0 = DC (the root's value), then the AC coefficients in the
+// order they are made (step by step, within a step in Morton order).  FP64
+// arithmetic in exactly the order above, FP32 storage.  The inverse undoes
+// the merges in reverse:  a1 = (sqrt(w1) L - sqrt(w2) H) / sqrt(w1 + w2),
+//                         a2 = (sqrt(w2) L + sqrt(w1) H) / sqrt(w1 + w2).
 //
-// Each step is three launches over the live-node list: pair flags and block
-// sums, a one-block scan of the block sums (which also advances the live and
-// AC counts kept on the device), and the merges with the compaction of the
-// list.  Nothing is read back to the host between steps.  Consecutive lanes
-// take consecutive live nodes, so the list, the codes and (while the live
-// slots are dense) the values are read coalesced.
+// The merge structure follows from the codes alone, without running the
+// steps: every merge joins the leaves on the two sides of one boundary i
+// between neighbouring codes (N - 1 boundaries, N - 1 merges).  With d the
+// highest bit in which code[i] and code[i + 1] differ, the merge happens at
+// step d and joins the leaves [L, i] and [i + 1, R], the run of codes that
+// agree with code[i] above bit d (every boundary inside either side differs
+// lower, so each side is one node by then): L and R are binary searches in
+// the sorted codes, the weights are i - L + 1 and R - i, the slots L and
+// i + 1.  The AC index of the merge is its rank in (step, boundary) order:
+// per-block counts of each step, a scan over (step, block), and a scatter
+// that ranks a block's boundaries of each step with wavefront ballots.  The
+// values then go through one launch per step over that step's merges only;
+// they are stored node-major ([N][C]) and a merge is done by a team of lanes,
+// one per channel, so its two nodes' rows are read and written whole however
+// far apart the nodes are (with one node per lane and channel-major values a
+// merge touched a separate cache line per channel and node).
 #include <cstring>
 
 #include "common.h"
@@ -33,258 +42,331 @@ namespace mgs {
 namespace {
 
 constexpr int RH_THREADS = 256;
-constexpr int RH_ITEMS = 8;                          // live nodes per thread
+constexpr int RH_ITEMS = 8;                          // boundaries per thread
 constexpr int RH_SPAN = RH_THREADS * RH_ITEMS;       // per block
-constexpr int RH_MAX_BLOCKS = RH_THREADS * 16;       // one-block scan capacity
+constexpr int RH_MAX_BLOCKS = 4096;                  // N - 1 <= RH_SPAN * RH_MAX_BLOCKS
+constexpr int RH_BINS = 64;                          // merge steps (3 depth <= 63)
+constexpr int RH_TEAM = 32;                          // lanes per merge (one channel each)
+constexpr int RH_TEAMS = RH_THREADS / RH_TEAM;
+constexpr int RH_GROUP = 16;                         // consecutive merges per block iteration
 
 struct RahtArgs {
     const uint64_t* codes;
     int64_t N;
     int32_t C;
+    int32_t depth;
     int64_t ld;
     const float* attr;     // forward input [C][ld]
     const float* coef_in;  // inverse input [C][ld]
     float* coef;           // forward output [C][ld]
     float* attr_out;       // inverse output [C][ld]
-    double* val;           // [C][N] node values by slot
-    int64_t* w;            // [N] node weights by slot
-    int32_t* live[2];      // live slot lists (ping-pong)
-    int64_t* bsum;         // [nblk] packed block sums: pairs | kept << 32
-    int64_t* n_live;       // [steps + 1]
-    int64_t* ac_base;      // [steps + 1]
-    int32_t* pa;           // [N] per AC index: first slot of the pair
-    int32_t* pb;           //                   second slot
-    int64_t* wa;           //                   weights
+    double* val;           // [N][C] node values by slot (a node's channels adjacent)
+    uint8_t* dstep;        // [N - 1] merge step of each boundary
+    int32_t* lb;           // [N - 1] first leaf of each boundary's merge
+    int32_t* rb;           // [N - 1] last leaf
+    int64_t* cnt;          // [RH_BINS][nblk] boundaries per (step, block), then their first AC index
+    int64_t* tot;          // [RH_BINS] boundaries per step
+    int64_t* ac_base;      // [RH_BINS + 1] first AC index of each step
+    int32_t* pa;           // [N - 1] per AC index: slot of the first node
+    int32_t* pb;           //                       slot of the second node
+    int64_t* wa;           //                       weights
     int64_t* wb;
     mgs_status_block* status;
-    int32_t nblk;
-    int32_t values;        // forward pass also carries the values
+    int32_t nblk;          // blocks over the N - 1 boundaries
+    int32_t values;        // forward: the leaves' values are loaded
 };
 
-// Slot list, weights and values of the leaves; the codes must increase.
-__global__ void raht_init_kernel(RahtArgs a, int depth) {
-    const int64_t lim = depth >= 21 ? 0 : ((int64_t)1 << (3 * depth));
+// Leaf values; the codes must increase and stay below 2^(3 depth).
+__global__ void raht_init_kernel(RahtArgs a) {
+    const int64_t lim = a.depth >= 21 ? 0 : ((int64_t)1 << (3 * a.depth));
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N;
          i += (int64_t)gridDim.x * blockDim.x) {
-        a.live[0][i] = (int32_t)i;
-        a.w[i] = 1;
         const uint64_t c = a.codes[i];
         if ((i > 0 && a.codes[i - 1] >= c) || (lim && c >= (uint64_t)lim)) atomicOr(&a.status->nonfinite, 4u);
         if (a.values)
-            for (int k = 0; k < a.C; ++k) a.val[(int64_t)k * a.N + i] = (double)a.attr[(int64_t)k * a.ld + i];
+            for (int k = 0; k < a.C; ++k) a.val[i * a.C + k] = (double)a.attr[(int64_t)k * a.ld + i];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.n_live[0] = a.N;
-        a.ac_base[0] = 0;
-    }
+    if (blockIdx.x == 0)
+        for (int b = threadIdx.x; b < RH_BINS; b += blockDim.x) a.tot[b] = 0;
 }
 
-// Live node i at step s: first of a pair (bit s clear, the next live node
-// has the same parent) or second of one.
-struct PairFlags {
-    bool first, second;
+// The merge across boundary i: its step d and the leaf range [L, R] it joins
+// ([L, i] first node, [i + 1, R] second).  Codes that do not increase give a
+// harmless stand-in (d = 0, L = i, R = i + 1; the status flag is raised by
+// the init kernel) so every index stays in bounds.
+struct Boundary {
+    int d;
+    int64_t L, R;
 };
 
-__device__ __forceinline__ PairFlags pair_flags(const RahtArgs& a, const int32_t* live, int64_t n, int64_t i,
-                                                int s) {
-    const uint64_t key = a.codes[live[i]] >> s;
-    PairFlags f{false, false};
-    if ((key & 1u) == 0) {
-        f.first = i + 1 < n && (a.codes[live[i + 1]] >> s) >> 1 == key >> 1;
-    } else {
-        f.second = i > 0 && (a.codes[live[i - 1]] >> s) >> 1 == key >> 1;
+__device__ __forceinline__ int boundary_step(const RahtArgs& a, int64_t i) {
+    const uint64_t c0 = a.codes[i], c1 = a.codes[i + 1];
+    if (c1 <= c0) return 0;
+    const int d = 63 - __clzll((long long)(c0 ^ c1));
+    return d >= 3 * a.depth ? RH_BINS - 1 : d;  // beyond the grid: never merged (flagged by init)
+}
+
+__device__ __forceinline__ Boundary boundary(const RahtArgs& a, int64_t i) {
+    const uint64_t c0 = a.codes[i], c1 = a.codes[i + 1];
+    Boundary b{0, i, i + 1};
+    if (c1 <= c0) return b;
+    const int d = 63 - __clzll((long long)(c0 ^ c1));
+    if (d >= 3 * a.depth) {
+        b.d = RH_BINS - 1;
+        return b;
     }
-    return f;
+    b.d = d;
+    const int sh = d + 1;                              // <= 63
+    const uint64_t lo_code = (c0 >> sh) << sh;         // first code of the run
+    const uint64_t hi_code = lo_code + (1ull << sh);   // first code past it
+    // a run spans at most 2^sh codes, hence at most that many leaves
+    const int64_t span = sh >= 62 ? a.N : std::min<int64_t>(a.N, (int64_t)1 << sh);
+    // L: first j in [max(0, i + 1 - span), i] with code[j] >= lo_code
+    int64_t lo = std::max<int64_t>(0, i + 1 - span), hi = i;
+    while (lo < hi) {
+        const int64_t m = lo + ((hi - lo) >> 1);
+        if (a.codes[m] >= lo_code) hi = m;
+        else lo = m + 1;
+    }
+    b.L = lo;
+    // R: last j in [i + 1, min(N - 1, i + span)] with code[j] < hi_code
+    lo = i + 1;
+    hi = std::min<int64_t>(a.N - 1, i + span);
+    while (lo < hi) {
+        const int64_t m = lo + ((hi - lo + 1) >> 1);
+        if (a.codes[m] < hi_code) lo = m;
+        else hi = m - 1;
+    }
+    b.R = lo;
+    return b;
 }
 
-__device__ __forceinline__ int64_t block_sum_i64(int64_t v) {
-    __shared__ int64_t part[RH_THREADS / MGS_WAVE];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, MGS_WAVE);
-    if ((threadIdx.x & (MGS_WAVE - 1)) == 0) part[threadIdx.x / MGS_WAVE] = v;
+// Boundaries of each step in this block (boundary i = blockIdx.x * RH_SPAN +
+// e * RH_THREADS + threadIdx.x).
+__global__ __launch_bounds__(RH_THREADS) void raht_count_kernel(RahtArgs a) {
+    __shared__ uint32_t h[RH_BINS];
+    for (int b = threadIdx.x; b < RH_BINS; b += RH_THREADS) h[b] = 0u;
     __syncthreads();
-    int64_t t = 0;
-#pragma unroll
-    for (int k = 0; k < RH_THREADS / MGS_WAVE; ++k) t += part[k];
+    const int64_t i0 = (int64_t)blockIdx.x * RH_SPAN + threadIdx.x;
+    for (int e = 0; e < RH_ITEMS; ++e) {
+        const int64_t i = i0 + (int64_t)e * RH_THREADS;
+        if (i >= a.N - 1) break;
+        const int d = boundary_step(a, i);
+        a.dstep[i] = (uint8_t)d;
+        atomicAdd(&h[d], 1u);
+    }
     __syncthreads();
-    return t;
+    for (int b = threadIdx.x; b < RH_BINS; b += RH_THREADS) {
+        a.cnt[(int64_t)b * a.nblk + blockIdx.x] = h[b];
+        if (h[b]) atomicAdd((unsigned long long*)&a.tot[b], (unsigned long long)h[b]);
+    }
 }
 
-// Exclusive scan of one value per thread over the block; also the total.
-__device__ __forceinline__ int64_t block_exscan_i64(int64_t v, int64_t& total) {
-    __shared__ int64_t sc[RH_THREADS];
-    sc[threadIdx.x] = v;
+// The leaf range of every boundary's merge (one boundary per thread: the
+// binary searches of many boundaries are in flight at once).
+__global__ void raht_bounds_kernel(RahtArgs a) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N - 1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Boundary b = boundary(a, i);
+        a.lb[i] = (int32_t)b.L;
+        a.rb[i] = (int32_t)b.R;
+    }
+}
+
+// One block per step: the first AC index of each (step, block) -- the steps
+// before this one, then this step's counts of the earlier blocks -- in place,
+// and the first AC index of the step.
+__global__ __launch_bounds__(RH_THREADS) void raht_scan_kernel(RahtArgs a) {
+    __shared__ int64_t v[RH_MAX_BLOCKS];
+    __shared__ int64_t part[RH_THREADS];
+    const int st = blockIdx.x;
+    int64_t base = 0;
+    for (int b = 0; b < st; ++b) base += a.tot[b];
+    int64_t* c = a.cnt + (int64_t)st * a.nblk;
+    for (int j = threadIdx.x; j < a.nblk; j += RH_THREADS) v[j] = c[j];
+    __syncthreads();
+    constexpr int PER = RH_MAX_BLOCKS / RH_THREADS;
+    const int j0 = threadIdx.x * PER;
+    int64_t sum = 0;
+    for (int e = 0; e < PER; ++e)
+        if (j0 + e < a.nblk) sum += v[j0 + e];
+    part[threadIdx.x] = sum;
     __syncthreads();
     for (int o = 1; o < RH_THREADS; o <<= 1) {
-        const int64_t add = threadIdx.x >= (unsigned)o ? sc[threadIdx.x - o] : 0;
+        const int64_t add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
         __syncthreads();
-        sc[threadIdx.x] += add;
+        part[threadIdx.x] += add;
         __syncthreads();
     }
-    total = sc[RH_THREADS - 1];
-    const int64_t ex = sc[threadIdx.x] - v;
-    __syncthreads();
-    return ex;
-}
-
-__global__ __launch_bounds__(RH_THREADS) void raht_count_kernel(RahtArgs a, int s) {
-    const int32_t* live = a.live[s & 1];
-    const int64_t n = a.n_live[s];
-    int64_t v = 0;
-    const int64_t i0 = (int64_t)blockIdx.x * RH_SPAN + threadIdx.x;
-    for (int e = 0; e < RH_ITEMS; ++e) {
-        const int64_t i = i0 + (int64_t)e * RH_THREADS;
-        if (i >= n) break;
-        const PairFlags f = pair_flags(a, live, n, i, s);
-        v += (int64_t)f.first + ((int64_t)(!f.second) << 32);
-    }
-    v = block_sum_i64(v);
-    if (threadIdx.x == 0) a.bsum[blockIdx.x] = v;
-}
-
-// One block: exclusive scan of the block sums in place; the next live count
-// and the AC base of the next step.
-__global__ __launch_bounds__(RH_THREADS) void raht_scan_kernel(RahtArgs a, int s) {
-    constexpr int PER = RH_MAX_BLOCKS / RH_THREADS;
-    int64_t loc[PER];
-    int64_t t = 0;
-    for (int e = 0; e < PER; ++e) {
-        const int b = threadIdx.x * PER + e;
-        loc[e] = b < a.nblk ? a.bsum[b] : 0;
-        t += loc[e];
-    }
-    int64_t total = 0;
-    int64_t off = block_exscan_i64(t, total);
-    for (int e = 0; e < PER; ++e) {
-        const int b = threadIdx.x * PER + e;
-        if (b < a.nblk) a.bsum[b] = off;
-        off += loc[e];
-    }
-    if (threadIdx.x == 0) {
-        a.n_live[s + 1] = total >> 32;
-        a.ac_base[s + 1] = a.ac_base[s] + (total & 0xFFFFFFFFll);
-    }
-}
-
-// The block's live nodes are taken in rounds of RH_THREADS consecutive ones
-// (consecutive lanes, consecutive nodes: coalesced reads of the list, the
-// codes and the values); a node's output positions follow node order, from
-// wavefront ballots: per (round, wave) counts, one wavefront's exclusive scan
-// of them, plus the lanes below.
-__global__ __launch_bounds__(RH_THREADS) void raht_merge_kernel(RahtArgs a, int s) {
-    constexpr int NW = RH_THREADS / MGS_WAVE;
-    static_assert(RH_ITEMS * NW <= MGS_WAVE, "one (round, wave) count per lane of the scanning wavefront");
-    __shared__ int64_t off[RH_ITEMS * NW];
-    const int32_t* live = a.live[s & 1];
-    int32_t* next = a.live[(s + 1) & 1];
-    const int64_t n = a.n_live[s];
-    const int lane = threadIdx.x & (MGS_WAVE - 1), wave = threadIdx.x / MGS_WAVE;
-    const int64_t i0 = (int64_t)blockIdx.x * RH_SPAN + threadIdx.x;
-    uint64_t mf[RH_ITEMS], mk[RH_ITEMS];
-#pragma unroll
-    for (int e = 0; e < RH_ITEMS; ++e) {
-        const int64_t i = i0 + (int64_t)e * RH_THREADS;
-        const PairFlags f = i < n ? pair_flags(a, live, n, i, s) : PairFlags{false, true};
-        mf[e] = __ballot(f.first);
-        mk[e] = __ballot(!f.second);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int e = 0; e < RH_ITEMS; ++e)
-            off[e * NW + wave] = (int64_t)__popcll(mf[e]) + ((int64_t)__popcll(mk[e]) << 32);
-    }
-    __syncthreads();
-    if (wave == 0) {
-        const int64_t v = lane < RH_ITEMS * NW ? off[lane] : 0;
-        int64_t incl = v;
-#pragma unroll
-        for (int o = 1; o < MGS_WAVE; o <<= 1) {
-            const int64_t y = __shfl_up(incl, o, MGS_WAVE);
-            if (lane >= o) incl += y;
+    int64_t run = base + part[threadIdx.x] - sum;
+    for (int e = 0; e < PER; ++e)
+        if (j0 + e < a.nblk) {
+            const int64_t x = v[j0 + e];
+            v[j0 + e] = run;
+            run += x;
         }
-        if (lane < RH_ITEMS * NW) off[lane] = a.bsum[blockIdx.x] + incl - v;
-    }
     __syncthreads();
+    for (int j = threadIdx.x; j < a.nblk; j += RH_THREADS) c[j] = v[j];
+    if (threadIdx.x == 0) {
+        a.ac_base[st] = base;
+        if (st == RH_BINS - 1) a.ac_base[RH_BINS] = base + a.tot[st];
+    }
+}
+
+// Every boundary's merge at its AC index: the block's offset for the step,
+// plus the boundaries of that step in earlier (round, wave) pairs of the
+// block, plus the lanes below with the same step (lanes grouped by step with
+// six ballots, one per bit of the step).
+__global__ __launch_bounds__(RH_THREADS) void raht_pairs_kernel(RahtArgs a) {
+    constexpr int NW = RH_THREADS / MGS_WAVE;
+    __shared__ uint32_t cw[RH_ITEMS][NW][RH_BINS];
+    for (int j = threadIdx.x; j < RH_ITEMS * NW * RH_BINS; j += RH_THREADS) (&cw[0][0][0])[j] = 0u;
+    __syncthreads();
+    const int lane = threadIdx.x & (MGS_WAVE - 1), wave = threadIdx.x / MGS_WAVE;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t i0 = (int64_t)blockIdx.x * RH_SPAN + threadIdx.x;
+    int bin[RH_ITEMS];
+    uint32_t rank[RH_ITEMS];
 #pragma unroll
     for (int e = 0; e < RH_ITEMS; ++e) {
         const int64_t i = i0 + (int64_t)e * RH_THREADS;
-        if (i >= n) continue;
-        const int64_t o = off[e * NW + wave];
-        const int32_t sa = live[i];
-        if ((mf[e] >> lane) & 1ull) {
-            const int64_t pos_pair = a.ac_base[s] + (o & 0xFFFFFFFFll) + __popcll(mf[e] & lt);
-            const int32_t sb = live[i + 1];
-            const int64_t w1 = a.w[sa], w2 = a.w[sb];
-            a.pa[pos_pair] = sa;
-            a.pb[pos_pair] = sb;
-            a.wa[pos_pair] = w1;
-            a.wb[pos_pair] = w2;
-            if (a.values) {
-                const double s1 = sqrt((double)w1), s2 = sqrt((double)w2), sw = sqrt((double)(w1 + w2));
-#pragma unroll 4
-                for (int k = 0; k < a.C; ++k) {
-                    const double a1 = a.val[(int64_t)k * a.N + sa], a2 = a.val[(int64_t)k * a.N + sb];
+        const bool valid = i < a.N - 1;
+        const int b = valid ? (int)a.dstep[i] : 0;
+        bin[e] = b;
+        uint64_t eq = __ballot(valid);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const uint64_t m = __ballot(valid && ((b >> k) & 1));
+            eq &= ((b >> k) & 1) ? m : ~m;
+        }
+        rank[e] = (uint32_t)__popcll(eq & lt);
+        if (valid && (eq & lt) == 0ull) cw[e][wave][b] = (uint32_t)__popcll(eq);
+    }
+    __syncthreads();
+    if (threadIdx.x < RH_BINS) {
+        uint32_t run = 0;
+        for (int e = 0; e < RH_ITEMS; ++e)
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t v = cw[e][w][threadIdx.x];
+                cw[e][w][threadIdx.x] = run;
+                run += v;
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < RH_ITEMS; ++e) {
+        const int64_t i = i0 + (int64_t)e * RH_THREADS;
+        if (i >= a.N - 1) continue;
+        const int b = bin[e];
+        const int64_t p = a.cnt[(int64_t)b * a.nblk + blockIdx.x] + cw[e][wave][b] + rank[e];
+        const int64_t L = a.lb[i], R = a.rb[i];
+        a.pa[p] = (int32_t)L;
+        a.pb[p] = (int32_t)(i + 1);
+        a.wa[p] = i - L + 1;
+        a.wb[p] = R - i;
+    }
+}
+
+// The merges of step s (independent of each other), RH_GROUP consecutive AC
+// indices per block iteration: a team of RH_TEAM lanes takes one merge, lane
+// k channel k (channels beyond the team in further rounds), so the two
+// nodes' rows are read and written whole; the coefficients of the group go
+// through LDS and out as runs of consecutive AC indices per channel.
+__global__ __launch_bounds__(RH_THREADS) void raht_merge_kernel(RahtArgs a, int s) {
+    __shared__ float hs[RH_TEAM][RH_GROUP];
+    const int64_t b0 = a.ac_base[s], b1 = a.ac_base[s + 1];
+    const int team = threadIdx.x / RH_TEAM, tl = threadIdx.x % RH_TEAM;
+    for (int64_t g0 = b0 + (int64_t)blockIdx.x * RH_GROUP; g0 < b1; g0 += (int64_t)gridDim.x * RH_GROUP) {
+        const int ng = (int)std::min<int64_t>(RH_GROUP, b1 - g0);
+        for (int k0 = 0; k0 < a.C; k0 += RH_TEAM) {
+            const int k = k0 + tl;
+            for (int q = team; q < ng; q += RH_TEAMS) {
+                const int64_t p = g0 + q;
+                const int32_t sa = a.pa[p], sb = a.pb[p];
+                const int64_t w1 = a.wa[p], w2 = a.wb[p];
+                if (k < a.C) {
+                    const double s1 = sqrt((double)w1), s2 = sqrt((double)w2), sw = sqrt((double)(w1 + w2));
+                    double* va = a.val + (int64_t)sa * a.C;
+                    const double a1 = va[k], a2 = a.val[(int64_t)sb * a.C + k];
                     const double L = (s1 * a1 + s2 * a2) / sw;
                     const double H = (s1 * a2 - s2 * a1) / sw;
-                    a.val[(int64_t)k * a.N + sa] = L;
-                    a.coef[(int64_t)k * a.ld + 1 + pos_pair] = (float)H;
+                    va[k] = L;
+                    hs[tl][q] = (float)H;
                 }
             }
-            a.w[sa] = w1 + w2;
+            __syncthreads();
+            const int nk = std::min(RH_TEAM, a.C - k0);
+            for (int j = threadIdx.x; j < nk * RH_GROUP; j += RH_THREADS) {
+                const int kk = j / RH_GROUP, q = j % RH_GROUP;
+                if (q < ng) a.coef[(int64_t)(k0 + kk) * a.ld + 1 + g0 + q] = hs[kk][q];
+            }
+            __syncthreads();
         }
-        if ((mk[e] >> lane) & 1ull) next[(o >> 32) + __popcll(mk[e] & lt)] = sa;
     }
 }
 
 // DC coefficients: the value of the root (slot of the first leaf).
 __global__ void raht_dc_kernel(RahtArgs a) {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.C; k += gridDim.x * blockDim.x)
-        a.coef[(int64_t)k * a.ld] = (float)a.val[(int64_t)k * a.N];
+        a.coef[(int64_t)k * a.ld] = (float)a.val[k];  // slot 0, channel k
 }
 
 // Inverse: the root's value from the DC, then the merges of one step undone
 // (steps in reverse order; the merges of a step are independent).
 __global__ void raht_inv_init_kernel(RahtArgs a) {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.C; k += gridDim.x * blockDim.x)
-        a.val[(int64_t)k * a.N] = (double)a.coef_in[(int64_t)k * a.ld];
+        a.val[k] = (double)a.coef_in[(int64_t)k * a.ld];
 }
 
-__global__ void raht_unmerge_kernel(RahtArgs a, int s) {
+// The inverse of one step in the same layout: the group's coefficients come
+// in through LDS as runs per channel, a team undoes one merge.
+__global__ __launch_bounds__(RH_THREADS) void raht_unmerge_kernel(RahtArgs a, int s) {
+    __shared__ float hs[RH_TEAM][RH_GROUP];
     const int64_t b0 = a.ac_base[s], b1 = a.ac_base[s + 1];
-    for (int64_t p = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < b1;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t sa = a.pa[p], sb = a.pb[p];
-        const int64_t w1 = a.wa[p], w2 = a.wb[p];
-        const double s1 = sqrt((double)w1), s2 = sqrt((double)w2), sw = sqrt((double)(w1 + w2));
-#pragma unroll 4
-        for (int k = 0; k < a.C; ++k) {
-            const double L = a.val[(int64_t)k * a.N + sa];
-            const double H = (double)a.coef_in[(int64_t)k * a.ld + 1 + p];
-            a.val[(int64_t)k * a.N + sa] = (s1 * L - s2 * H) / sw;
-            a.val[(int64_t)k * a.N + sb] = (s2 * L + s1 * H) / sw;
+    const int team = threadIdx.x / RH_TEAM, tl = threadIdx.x % RH_TEAM;
+    for (int64_t g0 = b0 + (int64_t)blockIdx.x * RH_GROUP; g0 < b1; g0 += (int64_t)gridDim.x * RH_GROUP) {
+        const int ng = (int)std::min<int64_t>(RH_GROUP, b1 - g0);
+        for (int k0 = 0; k0 < a.C; k0 += RH_TEAM) {
+            const int nk = std::min(RH_TEAM, a.C - k0);
+            for (int j = threadIdx.x; j < nk * RH_GROUP; j += RH_THREADS) {
+                const int kk = j / RH_GROUP, q = j % RH_GROUP;
+                if (q < ng) hs[kk][q] = a.coef_in[(int64_t)(k0 + kk) * a.ld + 1 + g0 + q];
+            }
+            __syncthreads();
+            const int k = k0 + tl;
+            for (int q = team; q < ng; q += RH_TEAMS) {
+                const int64_t p = g0 + q;
+                const int32_t sa = a.pa[p], sb = a.pb[p];
+                const int64_t w1 = a.wa[p], w2 = a.wb[p];
+                if (k < a.C) {
+                    const double s1 = sqrt((double)w1), s2 = sqrt((double)w2), sw = sqrt((double)(w1 + w2));
+                    double* va = a.val + (int64_t)sa * a.C;
+                    const double L = va[k];
+                    const double H = (double)hs[tl][q];
+                    va[k] = (s1 * L - s2 * H) / sw;
+                    a.val[(int64_t)sb * a.C + k] = (s2 * L + s1 * H) / sw;
+                }
+            }
+            __syncthreads();
         }
     }
 }
 
 __global__ void raht_store_kernel(RahtArgs a) {
-    const int64_t total = (int64_t)a.C * a.N;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = i / a.N, j = i - k * a.N;
-        a.attr_out[k * a.ld + j] = (float)a.val[i];
-    }
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.N;
+         j += (int64_t)gridDim.x * blockDim.x)
+        for (int k = 0; k < a.C; ++k) a.attr_out[(int64_t)k * a.ld + j] = (float)a.val[j * a.C + k];
 }
 
 struct RahtLayout {
-    size_t val, w, live0, live1, bsum, counts, pa, pb, wa, wb, total;
+    size_t val, dstep, lb, rb, cnt, tot, ac, pa, pb, wa, wb, total;
     int nblk, steps;
 };
 
 RahtLayout raht_layout(int64_t N, int32_t C, int32_t depth) {
     RahtLayout L;
     const size_t n = (size_t)std::max<int64_t>(N, 1);
-    L.nblk = (int)((N + RH_SPAN - 1) / RH_SPAN);
+    L.nblk = (int)((N - 1 + RH_SPAN - 1) / RH_SPAN);
     L.steps = 3 * depth;
     size_t o = MGS_STATUS_BYTES;
     auto take = [&](size_t bytes) {
@@ -293,11 +375,12 @@ RahtLayout raht_layout(int64_t N, int32_t C, int32_t depth) {
         return at;
     };
     L.val = take(sizeof(double) * n * (size_t)C);
-    L.w = take(sizeof(int64_t) * n);
-    L.live0 = take(sizeof(int32_t) * n);
-    L.live1 = take(sizeof(int32_t) * n);
-    L.bsum = take(sizeof(int64_t) * (size_t)std::max(L.nblk, 1));
-    L.counts = take(sizeof(int64_t) * 2 * (size_t)(L.steps + 1));
+    L.dstep = take(n);
+    L.lb = take(sizeof(int32_t) * n);
+    L.rb = take(sizeof(int32_t) * n);
+    L.cnt = take(sizeof(int64_t) * (size_t)RH_BINS * (size_t)std::max(L.nblk, 1));
+    L.tot = take(sizeof(int64_t) * RH_BINS);
+    L.ac = take(sizeof(int64_t) * (RH_BINS + 1));
     L.pa = take(sizeof(int32_t) * n);
     L.pb = take(sizeof(int32_t) * n);
     L.wa = take(sizeof(int64_t) * n);
@@ -310,15 +393,16 @@ unsigned rh_grid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
 }
 
-// The merge steps; with values the forward transform, without them only the
-// structure (for the inverse).
-int raht_steps(RahtArgs& a, const RahtLayout& L, int depth, hipStream_t s) {
-    hipLaunchKernelGGL(raht_init_kernel, dim3(rh_grid(a.N)), dim3(256), 0, s, a, depth);
-    for (int st = 0; st < L.steps; ++st) {
-        hipLaunchKernelGGL(raht_count_kernel, dim3(L.nblk), dim3(RH_THREADS), 0, s, a, st);
-        hipLaunchKernelGGL(raht_scan_kernel, dim3(1), dim3(RH_THREADS), 0, s, a, st);
-        hipLaunchKernelGGL(raht_merge_kernel, dim3(L.nblk), dim3(RH_THREADS), 0, s, a, st);
+// Leaf values (forward) and the merge structure: every merge's step, slots
+// and weights at its AC index.
+int raht_structure(RahtArgs& a, const RahtLayout& L, hipStream_t s) {
+    hipLaunchKernelGGL(raht_init_kernel, dim3(rh_grid(a.N)), dim3(256), 0, s, a);
+    if (L.nblk > 0) {
+        hipLaunchKernelGGL(raht_count_kernel, dim3(L.nblk), dim3(RH_THREADS), 0, s, a);
+        hipLaunchKernelGGL(raht_bounds_kernel, dim3(rh_grid(a.N - 1)), dim3(256), 0, s, a);
     }
+    hipLaunchKernelGGL(raht_scan_kernel, dim3(RH_BINS), dim3(RH_THREADS), 0, s, a);
+    if (L.nblk > 0) hipLaunchKernelGGL(raht_pairs_kernel, dim3(L.nblk), dim3(RH_THREADS), 0, s, a);
     return mgs_last_launch();
 }
 
@@ -334,14 +418,15 @@ int raht_setup(RahtArgs& a, RahtLayout& L, const uint64_t* codes, int64_t N, int
     a.codes = codes;
     a.N = N;
     a.C = C;
+    a.depth = depth;
     a.ld = ld;
     a.val = (double*)(ws + L.val);
-    a.w = (int64_t*)(ws + L.w);
-    a.live[0] = (int32_t*)(ws + L.live0);
-    a.live[1] = (int32_t*)(ws + L.live1);
-    a.bsum = (int64_t*)(ws + L.bsum);
-    a.n_live = (int64_t*)(ws + L.counts);
-    a.ac_base = a.n_live + (L.steps + 1);
+    a.dstep = (uint8_t*)(ws + L.dstep);
+    a.lb = (int32_t*)(ws + L.lb);
+    a.rb = (int32_t*)(ws + L.rb);
+    a.cnt = (int64_t*)(ws + L.cnt);
+    a.tot = (int64_t*)(ws + L.tot);
+    a.ac_base = (int64_t*)(ws + L.ac);
     a.pa = (int32_t*)(ws + L.pa);
     a.pb = (int32_t*)(ws + L.pb);
     a.wa = (int64_t*)(ws + L.wa);
@@ -372,8 +457,10 @@ extern "C" int mgs_raht_forward(const uint64_t* d_codes, int64_t N, int32_t C, i
     a.coef = d_coef;
     a.values = 1;
     rc = mgs_fill<uint32_t>((uint32_t*)d_ws, 64, 0u, s);
-    if (!rc) rc = raht_steps(a, L, depth, s);
+    if (!rc) rc = raht_structure(a, L, s);
     if (rc) return rc;
+    for (int st = 0; st < L.steps; ++st)
+        hipLaunchKernelGGL(raht_merge_kernel, dim3(rh_grid(N / 2 + 1)), dim3(RH_THREADS), 0, s, a, st);
     hipLaunchKernelGGL(raht_dc_kernel, dim3(1), dim3(64), 0, s, a);
     return mgs_last_launch();
 }
@@ -391,11 +478,11 @@ extern "C" int mgs_raht_inverse(const uint64_t* d_codes, int64_t N, int32_t C, i
     a.attr_out = d_attr;
     a.values = 0;
     rc = mgs_fill<uint32_t>((uint32_t*)d_ws, 64, 0u, s);
-    if (!rc) rc = raht_steps(a, L, depth, s);
+    if (!rc) rc = raht_structure(a, L, s);
     if (rc) return rc;
     hipLaunchKernelGGL(raht_inv_init_kernel, dim3(1), dim3(64), 0, s, a);
     for (int st = L.steps - 1; st >= 0; --st)
-        hipLaunchKernelGGL(raht_unmerge_kernel, dim3(rh_grid(N / 2 + 1)), dim3(256), 0, s, a, st);
+        hipLaunchKernelGGL(raht_unmerge_kernel, dim3(rh_grid(N / 2 + 1)), dim3(RH_THREADS), 0, s, a, st);
     hipLaunchKernelGGL(raht_store_kernel, dim3(rh_grid((int64_t)C * N)), dim3(256), 0, s, a);
     return mgs_last_launch();
 }
