@@ -76,18 +76,41 @@ struct RahtArgs {
     int32_t values;        // forward: the leaves' values are loaded
 };
 
-// Leaf values; the codes must increase and stay below 2^(3 depth).
+// The codes must increase and stay below 2^(3 depth).
 __global__ void raht_init_kernel(RahtArgs a) {
     const int64_t lim = a.depth >= 21 ? 0 : ((int64_t)1 << (3 * a.depth));
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t c = a.codes[i];
         if ((i > 0 && a.codes[i - 1] >= c) || (lim && c >= (uint64_t)lim)) atomicOr(&a.status->nonfinite, 4u);
-        if (a.values)
-            for (int k = 0; k < a.C; ++k) a.val[i * a.C + k] = (double)a.attr[(int64_t)k * a.ld + i];
     }
     if (blockIdx.x == 0)
         for (int b = threadIdx.x; b < RH_BINS; b += blockDim.x) a.tot[b] = 0;
+}
+
+// Transposes between the [C][ld] FP32 attribute layout and the [N][C] FP64
+// node values through an LDS tile of 64 nodes x 32 channels, so that both
+// sides are read and written in runs.
+constexpr int RH_TILE_N = 64, RH_TILE_C = 32;
+
+__global__ __launch_bounds__(RH_THREADS) void raht_load_kernel(RahtArgs a) {
+    __shared__ double t[RH_TILE_C][RH_TILE_N + 1];
+    for (int64_t i0 = (int64_t)blockIdx.x * RH_TILE_N; i0 < a.N; i0 += (int64_t)gridDim.x * RH_TILE_N) {
+        const int nn = (int)std::min<int64_t>(RH_TILE_N, a.N - i0);
+        for (int k0 = 0; k0 < a.C; k0 += RH_TILE_C) {
+            const int nk = std::min(RH_TILE_C, a.C - k0);
+            for (int e = threadIdx.x; e < nk * RH_TILE_N; e += RH_THREADS) {
+                const int kk = e / RH_TILE_N, n = e % RH_TILE_N;
+                if (n < nn) t[kk][n] = (double)a.attr[(int64_t)(k0 + kk) * a.ld + i0 + n];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < nk * nn; e += RH_THREADS) {
+                const int n = e / nk, kk = e % nk;
+                a.val[(i0 + n) * a.C + k0 + kk] = t[kk][n];
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // The merge across boundary i: its step d and the leaf range [L, R] it joins
@@ -352,10 +375,24 @@ __global__ __launch_bounds__(RH_THREADS) void raht_unmerge_kernel(RahtArgs a, in
     }
 }
 
-__global__ void raht_store_kernel(RahtArgs a) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.N;
-         j += (int64_t)gridDim.x * blockDim.x)
-        for (int k = 0; k < a.C; ++k) a.attr_out[(int64_t)k * a.ld + j] = (float)a.val[j * a.C + k];
+__global__ __launch_bounds__(RH_THREADS) void raht_store_kernel(RahtArgs a) {
+    __shared__ double t[RH_TILE_C][RH_TILE_N + 1];
+    for (int64_t i0 = (int64_t)blockIdx.x * RH_TILE_N; i0 < a.N; i0 += (int64_t)gridDim.x * RH_TILE_N) {
+        const int nn = (int)std::min<int64_t>(RH_TILE_N, a.N - i0);
+        for (int k0 = 0; k0 < a.C; k0 += RH_TILE_C) {
+            const int nk = std::min(RH_TILE_C, a.C - k0);
+            for (int e = threadIdx.x; e < nk * nn; e += RH_THREADS) {
+                const int n = e / nk, kk = e % nk;
+                t[kk][n] = a.val[(i0 + n) * a.C + k0 + kk];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < nk * RH_TILE_N; e += RH_THREADS) {
+                const int kk = e / RH_TILE_N, n = e % RH_TILE_N;
+                if (n < nn) a.attr_out[(int64_t)(k0 + kk) * a.ld + i0 + n] = (float)t[kk][n];
+            }
+            __syncthreads();
+        }
+    }
 }
 
 struct RahtLayout {
@@ -397,6 +434,7 @@ unsigned rh_grid(int64_t n) {
 // and weights at its AC index.
 int raht_structure(RahtArgs& a, const RahtLayout& L, hipStream_t s) {
     hipLaunchKernelGGL(raht_init_kernel, dim3(rh_grid(a.N)), dim3(256), 0, s, a);
+    if (a.values) hipLaunchKernelGGL(raht_load_kernel, dim3(rh_grid(a.N / 4 + 1)), dim3(RH_THREADS), 0, s, a);
     if (L.nblk > 0) {
         hipLaunchKernelGGL(raht_count_kernel, dim3(L.nblk), dim3(RH_THREADS), 0, s, a);
         hipLaunchKernelGGL(raht_bounds_kernel, dim3(rh_grid(a.N - 1)), dim3(256), 0, s, a);
@@ -483,6 +521,6 @@ extern "C" int mgs_raht_inverse(const uint64_t* d_codes, int64_t N, int32_t C, i
     hipLaunchKernelGGL(raht_inv_init_kernel, dim3(1), dim3(64), 0, s, a);
     for (int st = L.steps - 1; st >= 0; --st)
         hipLaunchKernelGGL(raht_unmerge_kernel, dim3(rh_grid(N / 2 + 1)), dim3(RH_THREADS), 0, s, a, st);
-    hipLaunchKernelGGL(raht_store_kernel, dim3(rh_grid((int64_t)C * N)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(raht_store_kernel, dim3(rh_grid(N / 4 + 1)), dim3(RH_THREADS), 0, s, a);
     return mgs_last_launch();
 }
