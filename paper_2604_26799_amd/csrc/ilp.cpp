@@ -49,6 +49,7 @@ constexpr size_t kStateCap = 20u * 1000u * 1000u;
 // beam over a small core usually closes most of it for a fraction of what
 // such an exact pass costs).
 constexpr size_t kNoLimit = std::numeric_limits<size_t>::max();
+constexpr size_t kWideAfter = 512;  // core size from which a fruitless beam pass hands over
 constexpr struct { size_t beam, k0, exact_max; } kSchedules[] = {
     {1000, 32, 400}, {4000, 128, 1600}, {16000, 128, kNoLimit}};
 
@@ -645,6 +646,10 @@ struct Mckp {
             zb = e_fixed;
             for (size_t i = 0; i < core.size(); ++i) zb += err[core[i] * nopt + pick[i]];
             if (zb < UB) UB = zb;
+        } else if (K >= kWideAfter && exact_max != kNoLimit) {
+            // this beam found nothing better over a core of this size: a wider
+            // beam over a small core is the cheaper way on (the next schedule)
+            return MGS_ELIMIT;
         }
         K *= 4;
     }
