@@ -527,7 +527,8 @@ def test_vq_retain(torch, orc, remaining):
     assert np.array_equal(host(idx), widx)
 
 
-@pytest.mark.parametrize("n,depth,C", [(1, 4, 2), (3, 1, 1), (2000, 6, 3), (6000, 10, 2)])
+@pytest.mark.parametrize("n,depth,C", [(1, 4, 2), (3, 1, 1), (2000, 6, 3), (6000, 10, 2), (5000, 8, 40),
+                                       (40000, 14, 20), (4096, 21, 1)])
 def test_raht(torch, orc, n, depth, C):
     """RAHT forward: every coefficient bit-identical to the oracle (same FP64
     operations, FP32 storage); inverse: back to the attributes within FP32
