@@ -16,7 +16,10 @@ Batched mode (continuous batching):
   * each job's tables come back to pinned host memory and its ILP search runs
     on a host thread pool while the GPU keeps sweeping other jobs;
   * the chosen bit-widths go back, the final codes are quantized on the
-    device and copied to the host, and the job's memory is released.
+    device and copied to the host, and the job's memory is released;
+  * a launch whose status word flags non-finite data is swept again one job
+    per launch; a job with non-finite data fails (status ENONFINITE in its
+    result) and the stream goes on.
 Plain mode (the comparison): one job at a time, and one sweep launch per
 (reserve ratio, bit-width) candidate.
 
@@ -110,6 +113,7 @@ class _Live:
     t_swept: float = 0.0
     t_solved: float = 0.0
     status_h: object = None
+    batch_n: int = 0       # jobs in the sweep launch that computed its tables
 
 
 class SceneStore:
@@ -239,6 +243,7 @@ class Server:
                 b.host["err"].copy_(b.dev["out"]["err"], non_blocking=True)
                 b.host["bits"].copy_(b.dev["out"]["bits"], non_blocking=True)
                 b.status_h = status
+                b.batch_n = len(batch)
             ev = torch.cuda.Event()
             ev.record(self.compute)
         for b in batch:
@@ -314,13 +319,14 @@ class Server:
         pending = deque(sorted(jobs, key=lambda j: j.arrival_s))
         waiting: deque = deque()
         ready: List[_Live] = []
+        solo: deque = deque()
         sweeping: List[_Live] = []
         solving: List[_Live] = []
         coding: List[_Live] = []
         results: List[JobResult] = []
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
-        while pending or waiting or ready or sweeping or solving or coding:
+        while pending or waiting or ready or solo or sweeping or solving or coding:
             progressed = False
             tn = now()
             while pending and pending[0].arrival_s * time_scale <= tn:
@@ -338,6 +344,13 @@ class Server:
                 self._admit(live)
                 ready.append(live)
                 progressed = True
+            # jobs of a launch whose status word flagged non-finite data are
+            # swept again one per launch, so the flag names the job
+            while solo:
+                one = solo.popleft()
+                self._launch_sweep([one])
+                sweeping.append(one)
+                progressed = True
             # one sweep launch over every ready job (plain: the oldest one)
             if ready:
                 if self.mode == "batched":
@@ -352,7 +365,16 @@ class Server:
                 sweeping.remove(live)
                 live.t_swept = now()
                 if int(live.status_h[0]) != 0:
-                    raise mgs.MgsError(mgs.ENONFINITE, f"job {live.job.job_id}")
+                    if live.batch_n > 1:
+                        solo.append(live)  # which job of the launch: sweep it alone
+                    else:
+                        # this job's data is not finite: it fails, the stream goes on
+                        live.res = {"best_t": -1, "best_bits": None, "code": mgs.ENONFINITE}
+                        live.t_solved = now()
+                        live.ev = None
+                        coding.append(live)
+                    progressed = True
+                    continue
                 live.fut = self.pool.submit(self._solve, live)
                 solving.append(live)
                 progressed = True

@@ -57,3 +57,28 @@ def test_plain_mode_serves_every_job(store):
     for r in out["results"]:
         assert r.best_t >= 0 and r.codes.shape[0] == 20
         assert set(np.unique(r.best_bits)) <= set(range(2, 17))
+
+
+def test_nonfinite_job_fails_alone(store):
+    """A job whose scene holds a NaN fails with ENONFINITE; the stream goes on
+    and the other jobs of the same launch get the results they get on clean
+    data (the flagged launch is swept again one job per launch)."""
+    from paper_2604_26799_amd import mgs
+    bad = serve.SceneStore(num_bases=2, n=100_000)
+    bad.attr[1][3, 10] = float("nan")        # every job on base 1 sees it (n > 10)
+    jobs = synth.job_stream(6, 2.0, seed=5, n_lo=20_000, n_hi=100_000)
+    srv = serve.Server(bad, mode="batched", keep_codes=True)
+    out = srv.run(jobs, time_scale=0.0)       # all six in one launch
+    srv.close()
+    clean = serve.SceneStore(num_bases=2, n=100_000)
+    ref_srv = serve.Server(clean, mode="batched", keep_codes=True)
+    ref = {r.job_id: r for r in ref_srv.run(jobs, time_scale=0.0)["results"]}
+    ref_srv.close()
+    assert out["jobs"] == 6 and out["failed"] == 3
+    for r in out["results"]:
+        if jobs[r.job_id].base == 1:
+            assert r.status == mgs.ENONFINITE and r.best_t == -1 and r.best_bits is None
+        else:
+            assert r.status == mgs.OK and r.best_t == ref[r.job_id].best_t >= 0
+            assert np.array_equal(r.best_bits, ref[r.job_id].best_bits)
+            assert np.array_equal(r.codes, ref[r.job_id].codes)
