@@ -65,30 +65,50 @@ struct VqArgs {
 };
 
 // Prepared codebook and the codeword-norm maximum (the status word, the
-// maximum and the fallback counter are cleared before this kernel).
+// maximum and the fallback counter are cleared before this kernel).  One
+// thread per codeword; the loops run over the compile-time row width, so the
+// codeword's loads are all issued before use and its row is written as
+// 16-byte units.
+template <int KS>
 __global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
+    constexpr int KP = 16 * KS;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     float nrm = 0.0f;  // FP32 bits of non-negative floats order as unsigned ints
     if (j < a.Kpad) {
-        __bf16* row = a.cbp + (int64_t)j * a.KP;
+        bf16x8* row = (bf16x8*)(a.cbp + (int64_t)j * KP);
         if (j >= a.K) {
-            for (int k = 0; k < a.KP; ++k) row[k] = (__bf16)0.0f;
-            row[a.D] = (__bf16)1.0e30f;  // padding codewords score ~1e30 and are skipped
+#pragma unroll
+            for (int u = 0; u < KP / 8; ++u) {
+                bf16x8 z;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) z[i] = (__bf16)(8 * u + i == a.D ? 1.0e30f : 0.0f);
+                row[u] = z;  // padding codewords score ~1e30 and are skipped
+            }
         } else {
             const float* c = a.cb + (int64_t)j * a.D;
+            float v[KP];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) v[k] = k < a.D ? c[k] : 0.0f;
             double n2 = 0.0;
             bool bad = false;
-            for (int k = 0; k < a.D; ++k) {
-                float v = c[k];
-                bad |= !finite_f32(v);
-                n2 += (double)v * (double)v;
-                row[k] = (__bf16)(-2.0f * v);
+#pragma unroll
+            for (int k = 0; k < KP; ++k)
+                if (k < a.D) {
+                    bad |= !finite_f32(v[k]);
+                    n2 += (double)v[k] * (double)v[k];
+                }
+            const float hi = (float)(__bf16)(float)n2;
+            const float lo = (float)(n2 - (double)hi);
+#pragma unroll
+            for (int u = 0; u < KP / 8; ++u) {
+                bf16x8 w;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 8 * u + i;
+                    w[i] = (__bf16)(k < a.D ? -2.0f * v[k] : k == a.D ? hi : k == a.D + 1 ? lo : 0.0f);
+                }
+                row[u] = w;
             }
-            float hi = (float)(__bf16)(float)n2;
-            float lo = (float)(n2 - (double)hi);
-            row[a.D] = (__bf16)hi;
-            row[a.D + 1] = (__bf16)lo;
-            for (int k = a.D + 2; k < a.KP; ++k) row[k] = (__bf16)0.0f;
             if (bad) atomicOr(&a.status->nonfinite, 1u);
             nrm = (float)sqrt(n2) * (1.0f + 1.0e-6f);
         }
@@ -501,7 +521,14 @@ extern "C" int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float
     if (rc) return rc;
     rc = mgs_fill<uint32_t>(a.cmax_bits, 64, 0u, s);              // norm maximum + fallback count
     if (rc) return rc;
-    hipLaunchKernelGGL(vq_prep_kernel, dim3((L.Kpad + 255) / 256), dim3(256), 0, s, a);
+    const dim3 pgrid((L.Kpad + 255) / 256);
+    switch (L.KS) {
+        case 1: hipLaunchKernelGGL(vq_prep_kernel<1>, pgrid, dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(vq_prep_kernel<2>, pgrid, dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(vq_prep_kernel<3>, pgrid, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(vq_prep_kernel<4>, pgrid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(vq_prep_kernel<5>, pgrid, dim3(256), 0, s, a); break;
+    }
     if (N > 0) {
         const unsigned blocks = (unsigned)((N + VQ_ROWS - 1) / VQ_ROWS);
         switch (L.KS) {
