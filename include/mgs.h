@@ -343,8 +343,11 @@ int mgs_graph_destroy(void* graph);
  * Writes h_best_t, the chosen bit-widths h_best_bits[C][ceil(k_best / G)]
  * (caller sizes it for the largest k), per ratio h_obj[t] / h_used[t] (NaN / 0
  * unless solved) and, if h_status is not NULL, h_status[t] (MGS_SEARCH_*).
- * Host work runs on up to `threads` threads (0 = all cores).  Returns
- * MGS_EINFEASIBLE when no ratio is admissible.
+ * Host work runs on up to `threads` threads (0 = all cores); each of them
+ * keeps, between calls, the arrays of the largest LP bound it computed
+ * (about 100 bytes per class and option).  Returns MGS_EINFEASIBLE when no
+ * ratio is admissible, MGS_EINVAL when a loss is not finite or (size_mode 0)
+ * an entropy size is negative or not finite, in any ratio.
  * ====================================================================== */
 #define MGS_SEARCH_ALL 1            /* flags: solve every admissible ratio */
 #define MGS_SEARCH_SOLVED 0         /* h_status values */

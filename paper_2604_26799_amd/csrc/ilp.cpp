@@ -29,6 +29,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <memory>
 #include <numeric>
@@ -354,8 +355,10 @@ int core_dp(const std::vector<std::vector<Opt>>& opts, double e_fixed, int64_t c
 // One multiple-choice knapsack instance: prepare() runs the LP relaxation
 // (and returns early when the unconstrained optimum fits), exact() the DP.
 struct Mckp {
-    const double* err;
-    const int64_t* size;
+    // writes the nopt options (loss, size, original index) of class c; false
+    // if the class's inputs are invalid
+    using Fill = std::function<bool(int64_t c, Opt* o)>;
+    Fill fill;
     int64_t ncls;
     int nopt;
     int64_t budget;
@@ -374,17 +377,61 @@ struct Mckp {
         const Opt* end() const { return p + n; }
     };
     Span cls(int64_t c) const { return Span{opt.data() + coff[c], (int)(coff[c + 1] - coff[c])}; }
+    // option j (original index) of class c: a chosen option is never a
+    // dominated one, so it is among the kept options
+    const Opt& opt_j(int64_t c, int j) const {
+        const Span o = cls(c);
+        for (int i = 0; i + 1 < o.size(); ++i)
+            if (o[i].j == j) return o[i];
+        return o.back();
+    }
     std::vector<int> inc_pos, lagbest;
     std::vector<double> mlam, rcmin;
     std::vector<int64_t> order;
     double lambda = 0.0, LB0 = 0.0, UB = 0.0, tol = 0.0;
     bool trivial = false;  // the unconstrained optimum fits the budget
     std::vector<int> greedy_pos;  // LP greedy solution (its integral part)
+    // the LP step's lower hulls and its heap of next increments
+    struct Head {
+        double eff;
+        int64_t c;
+        int64_t h;  // index in hv of the increment's end vertex
+    };
+    struct Inc {
+        double eff;
+        int64_t ds;  // its size
+        int64_t c;
+        int64_t h;
+    };
+    std::vector<int> hv;
+    std::vector<int64_t> hoff;
+    std::vector<Head> heap;
+    std::vector<Inc> inc;  // every hull increment, for the selection
     int64_t greedy_cap = 0;       // capacity it leaves
     bool solve_ready = false;     // phase 2 done
 
-    Mckp(const double* e, const int64_t* s, int64_t n, int o, int64_t b)
-        : err(e), size(s), ncls(n), nopt(o), budget(b) {}
+    Mckp(const double* e, const int64_t* s, int64_t n, int o, int64_t b) : ncls(n), nopt(o), budget(b) {
+        fill = [e, s, o](int64_t c, Opt* x) {
+            for (int j = 0; j < o; ++j) x[j] = {e[c * o + j], s[c * o + j], j};
+            return true;
+        };
+    }
+    Mckp(Fill f, int64_t n, int o, int64_t b) : fill(std::move(f)), ncls(n), nopt(o), budget(b) {}
+    Mckp() : ncls(0), nopt(0), budget(0) {}
+
+    // Another instance in the same object: the arrays keep their capacity, so
+    // a long-lived object bounds one instance after another without fresh
+    // allocations.  Only prepare_bound may follow.
+    void rebind(Fill f, int64_t n, int o, int64_t b) {
+        fill = std::move(f);
+        ncls = n;
+        nopt = o;
+        budget = b;
+        lambda = LB0 = UB = tol = 0.0;
+        trivial = false;
+        solve_ready = false;
+        greedy_cap = 0;
+    }
 
     // Lower bound on the optimum (the optimum itself when trivial).
     double lower_bound() const { return LB0; }
@@ -407,7 +454,7 @@ struct Mckp {
     double max_obj = 0.0;
     Opt o[256];
     for (int64_t c = 0; c < ncls; ++c) {
-        for (int j = 0; j < nopt; ++j) o[j] = {err[c * nopt + j], size[c * nopt + j], j};
+        if (!fill(c, o)) return MGS_EINVAL;
         // insertion sort by (size, loss, index): the options of a class are
         // few and nearly sorted already (sizes grow with the bit-width)
         for (int i = 1; i < nopt; ++i) {
@@ -441,8 +488,8 @@ struct Mckp {
     // hull position, until one does not fit; its efficiency is lambda.  Each
     // class's increments are already in decreasing efficiency (convex hull),
     // so a heap merge of the classes yields that order and stops at the split.
-    std::vector<int> hv;                    // hull vertices (option positions), all classes
-    std::vector<int64_t> hoff(ncls + 1, 0);  // class c: hv[hoff[c] .. hoff[c+1])
+    hv.clear();                      // hull vertices (option positions), all classes
+    hoff.assign(ncls + 1, 0);        // class c: hv[hoff[c] .. hoff[c+1])
     hv.reserve((size_t)ncls * 4);
     for (int64_t c = 0; c < ncls; ++c) {
         const auto& o = cls(c);
@@ -462,47 +509,108 @@ struct Mckp {
         }
         hoff[c + 1] = (int64_t)hv.size();
     }
-    struct Head {
-        double eff;
-        int64_t c;
-        int64_t h;  // index in hv of the increment's end vertex
-    };
     auto eff_of = [&](int64_t c, int64_t h) {
         const Opt& a = cls(c)[hv[h - 1]];
         const Opt& b = cls(c)[hv[h]];
         return (a.e - b.e) / (double)(b.s - a.s);
     };
-    // max-heap on (eff, then smaller class first)
-    auto later = [](const Head& x, const Head& y) {
-        if (x.eff != y.eff) return x.eff < y.eff;
-        return x.c > y.c;
-    };
-    std::vector<Head> heap;
-    heap.reserve((size_t)ncls);
-    for (int64_t c = 0; c < ncls; ++c)
-        if (hoff[c + 1] - hoff[c] >= 2) heap.push_back({eff_of(c, hoff[c] + 1), c, hoff[c] + 1});
-    std::make_heap(heap.begin(), heap.end(), later);
-    std::vector<int> pos(ncls, 0);  // current option position per class
+    std::vector<int>& pos = greedy_pos;  // current option position per class
+    pos.assign(ncls, 0);
     int64_t cap = budget - min_total;
     lambda = 0.0;
-    while (!heap.empty()) {
-        std::pop_heap(heap.begin(), heap.end(), later);
-        const Head hd = heap.back();
-        heap.pop_back();
-        const int from = hv[hd.h - 1], to = hv[hd.h];
-        const int64_t ds = cls(hd.c)[to].s - cls(hd.c)[from].s;
-        if (ds > cap) {
-            lambda = hd.eff;
-            break;
+    // The greedy takes the increments in the order of a heap merge of the
+    // classes (largest efficiency first, ties to the smaller class).  When the
+    // efficiencies fall along every class's hull -- always so in exact
+    // arithmetic, rounding may break it -- that order is the sort by
+    // (efficiency desc, class, hull position), and the increment where the
+    // greedy stops (the first whose size no longer fits) is found by a
+    // weighted selection in linear expected time.
+    inc.clear();
+    bool monotone = true;
+    for (int64_t c = 0; c < ncls && monotone; ++c)
+        for (int64_t h = hoff[c] + 1; h < hoff[c + 1]; ++h) {
+            const double e = eff_of(c, h);
+            if (h > hoff[c] + 1 && e > inc.back().eff) {
+                monotone = false;
+                break;
+            }
+            inc.push_back({e, cls(c)[hv[h]].s - cls(c)[hv[h - 1]].s, c, h});
         }
-        cap -= ds;
-        pos[hd.c] = to;
-        if (hd.h + 1 < hoff[hd.c + 1]) {
-            heap.push_back({eff_of(hd.c, hd.h + 1), hd.c, hd.h + 1});
-            std::push_heap(heap.begin(), heap.end(), later);
+    if (monotone) {
+        auto before = [](const Inc& x, const Inc& y) {
+            if (x.eff != y.eff) return x.eff > y.eff;
+            if (x.c != y.c) return x.c < y.c;
+            return x.h < y.h;
+        };
+        // Invariant: the increments ordered before [lo, hi) are taken (their
+        // sizes are off cap), those after it are not.
+        size_t lo = 0, hi = inc.size();
+        bool stop = false;
+        Inc split{};
+        while (lo < hi) {
+            const size_t m = lo + (hi - lo) / 2, l = hi - 1;  // median of three as the pivot
+            size_t piv = m;
+            if (before(inc[lo], inc[m]) != before(inc[lo], inc[l])) piv = lo;
+            else if (before(inc[l], inc[m]) != before(inc[l], inc[lo])) piv = l;
+            std::swap(inc[lo], inc[piv]);
+            const Inc p = inc[lo];
+            size_t q = lo + 1;
+            int64_t w = 0;  // size of the increments before the pivot
+            for (size_t i = lo + 1; i < hi; ++i)
+                if (before(inc[i], p)) {
+                    w += inc[i].ds;
+                    std::swap(inc[i], inc[q++]);
+                }
+            if (w > cap) {  // the stop lies before the pivot
+                hi = q;
+                lo = lo + 1;
+            } else if (p.ds > cap - w) {  // the pivot is the stop
+                cap -= w;
+                split = p;
+                stop = true;
+                break;
+            } else {
+                cap -= w + p.ds;
+                lo = q;
+            }
+        }
+        // each class's taken increments are a prefix of its hull
+        for (int64_t c = 0; c < ncls; ++c) {
+            int64_t h = hoff[c] + 1;
+            for (; h < hoff[c + 1]; ++h)
+                if (stop && !before(Inc{eff_of(c, h), 0, c, h}, split)) break;
+            pos[c] = hv[h - 1];
+        }
+        if (stop) lambda = split.eff;
+    } else {
+        // max-heap on (eff, then smaller class first)
+        auto later = [](const Head& x, const Head& y) {
+            if (x.eff != y.eff) return x.eff < y.eff;
+            return x.c > y.c;
+        };
+        heap.clear();
+        heap.reserve((size_t)ncls);
+        for (int64_t c = 0; c < ncls; ++c)
+            if (hoff[c + 1] - hoff[c] >= 2) heap.push_back({eff_of(c, hoff[c] + 1), c, hoff[c] + 1});
+        std::make_heap(heap.begin(), heap.end(), later);
+        while (!heap.empty()) {
+            std::pop_heap(heap.begin(), heap.end(), later);
+            const Head hd = heap.back();
+            heap.pop_back();
+            const int from = hv[hd.h - 1], to = hv[hd.h];
+            const int64_t ds = cls(hd.c)[to].s - cls(hd.c)[from].s;
+            if (ds > cap) {
+                lambda = hd.eff;
+                break;
+            }
+            cap -= ds;
+            pos[hd.c] = to;
+            if (hd.h + 1 < hoff[hd.c + 1]) {
+                heap.push_back({eff_of(hd.c, hd.h + 1), hd.c, hd.h + 1});
+                std::push_heap(heap.begin(), heap.end(), later);
+            }
         }
     }
-    greedy_pos = std::move(pos);
     greedy_cap = cap;
 
     // ---- 3. Lagrangian bound, reduced costs, Lagrangian-best option per class
@@ -592,8 +700,9 @@ struct Mckp {
         double o = 0.0;
         int64_t u = 0;
         for (int64_t c = 0; c < ncls; ++c) {
-            o += err[c * nopt + choice[c]];
-            u += size[c * nopt + choice[c]];
+            const Opt& x = opt_j(c, choice[c]);
+            o += x.e;
+            u += x.s;
         }
         *obj = o;
         *used = u;
@@ -644,7 +753,7 @@ struct Mckp {
         }
         if (rc == MGS_OK) {
             zb = e_fixed;
-            for (size_t i = 0; i < core.size(); ++i) zb += err[core[i] * nopt + pick[i]];
+            for (size_t i = 0; i < core.size(); ++i) zb += opt_j(core[i], pick[i]).e;
             if (zb < UB) UB = zb;
         } else if (K >= kWideAfter && exact_max != kNoLimit) {
             // this beam found nothing better over a core of this size: a wider
@@ -747,13 +856,39 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
         if (d->h_bits[i] == 8) b8 = i;
     const int nthr = threads > 0 ? threads : omp_get_max_threads();
     std::vector<int> st(T, MGS_OK), state(T, MGS_SEARCH_SOLVED);
-    std::vector<std::vector<double>> E(T);
-    std::vector<std::vector<int64_t>> S(T);
-    std::vector<std::unique_ptr<Mckp>> inst(T);
-    std::vector<std::vector<uint8_t>> choice(T);
-    // ---- per ratio: tables, sizes, the doubled-8-bit test, LP bound
+    std::vector<double> lb(T, 0.0), lbtol(T, 0.0);
+    // The options of class (channel c, group g) of ratio t straight from the
+    // tables: loss row, and size by the rule of mgs_size_table.  False on a
+    // loss that is not finite or (entropy sizes) a size that is not finite
+    // and nonnegative.
+    auto filler = [&](int t) -> Mckp::Fill {
+        const int64_t k = d->h_k[t], ng = (k + G - 1) / G;
+        return [=](int64_t cls, Opt* o) {
+            const int64_t c = cls / ng, g = cls - c * ng;
+            const int64_t slot = ((int64_t)t * C + c) * gmaxn + g;
+            const double* e = h_err + slot * nb;
+            const double* b = h_bits + slot * nb;
+            const int64_t n = std::min<int64_t>(G, k - g * G);
+            bool ok = true;
+            for (int i = 0; i < nb; ++i) {
+                ok = ok && std::isfinite(e[i]) && (size_mode == 1 || (std::isfinite(b[i]) && b[i] >= 0));
+                o[i] = {e[i], size_mode == 0 ? (ok ? (int64_t)std::ceil(b[i]) : 0) + kMetaBits
+                                             : n * (int64_t)d->h_bits[i] + kMetaBits, i};
+            }
+            return ok;
+        };
+    };
+
+    // ---- per ratio: checks of the tables, the doubled-8-bit test, LP bound.
+    // Largest ratios first (the cost grows with k); each thread bounds its
+    // ratios in one long-lived instance, so that repeated searches reuse its
+    // arrays.
+    std::vector<int> by_k(T);
+    std::iota(by_k.begin(), by_k.end(), 0);
+    std::stable_sort(by_k.begin(), by_k.end(), [&](int a, int b) { return d->h_k[a] > d->h_k[b]; });
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
-    for (int t = 0; t < T; ++t) {
+    for (int i = 0; i < T; ++i) {
+        const int t = by_k[i];
         h_obj[t] = std::numeric_limits<double>::quiet_NaN();
         h_used[t] = 0;
         const int64_t k = d->h_k[t];
@@ -763,46 +898,62 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
             state[t] = MGS_SEARCH_SKIPPED;
             continue;
         }
-        std::vector<double> bt;
-        std::vector<int64_t> n;
-        S[t].resize(ncls * nb);
-        if (!ratio_instance(d, h_err, h_bits, t, gmaxn, E[t], bt, n)) {
+        // the all-8-bit size from the 8-bit column alone; every value of the
+        // ratio is checked by the bound's pass over the options, or by a pass
+        // of its own when the ratio is skipped
+        int64_t s8 = 0;
+        bool ok = true;
+        for (int c = 0; c < C; ++c)
+            for (int64_t g = 0; g < ng; ++g) {
+                const int64_t n = std::min<int64_t>(G, k - g * G);
+                if (b8 < 0 || size_mode == 1) {
+                    s8 += n * 8 + kMetaBits;
+                } else {
+                    const double b = h_bits[(((int64_t)t * C + c) * gmaxn + g) * nb + b8];
+                    if (std::isfinite(b) && b >= 0) s8 += (int64_t)std::ceil(b) + kMetaBits;
+                    else ok = false;
+                }
+            }
+        if (ok && 2 * s8 < budget_bits) {
+            Opt o[MGS_MAX_BITS];
+            const Mckp::Fill f = filler(t);
+            for (int64_t cls = 0; cls < ncls && ok; ++cls) ok = f(cls, o);
+            if (ok) {
+                state[t] = MGS_SEARCH_SKIPPED;
+                continue;
+            }
+        }
+        if (!ok) {
             st[t] = MGS_EINVAL;
             continue;
         }
-        int rc = mgs_size_table(bt.data(), n.data(), ncls, nb, d->h_bits, size_mode, S[t].data());
-        if (rc) {
-            st[t] = rc;
-            continue;
-        }
-        int64_t s8 = 0;  // the all-8-bit configuration
-        for (int64_t cls = 0; cls < ncls; ++cls)
-            s8 += (b8 >= 0) ? S[t][cls * nb + b8] : n[cls] * 8 + kMetaBits;
-        if (2 * s8 < budget_bits) {
-            state[t] = MGS_SEARCH_SKIPPED;
-            continue;
-        }
-        inst[t].reset(new Mckp(E[t].data(), S[t].data(), ncls, nb, budget_bits));
-        rc = inst[t]->prepare_bound();  // the rest only for the ratios that are solved
+        static thread_local Mckp wk;
+        wk.rebind(filler(t), ncls, nb, budget_bits);
+        const int rc = wk.prepare_bound();
         if (rc == MGS_EINFEASIBLE) state[t] = MGS_SEARCH_INFEASIBLE;
         else st[t] = rc;
+        lb[t] = wk.lower_bound();
+        lbtol[t] = wk.tol;
     }
     for (int t = 0; t < T; ++t)
         if (st[t] != MGS_OK) return st[t];
     // ---- exact solves: the ratio of least lower bound first, then (in
     // parallel) every ratio whose bound does not exceed that optimum -- the
-    // others cannot win (or tie) -- unless every ratio is asked for.
+    // others cannot win (or tie) -- unless every ratio is asked for.  A solved
+    // ratio builds its instance again (the same bound) and keeps its choice.
     std::vector<int> cand;
     for (int t = 0; t < T; ++t)
         if (state[t] == MGS_SEARCH_SOLVED) cand.push_back(t);
-    std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
-        return inst[a]->lower_bound() < inst[b]->lower_bound();
-    });
+    std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return lb[a] < lb[b]; });
+    std::vector<std::vector<uint8_t>> choice(T);
     auto solve_one = [&](int t) {
-        choice[t].resize(inst[t]->ncls);
+        const int64_t ncls = (int64_t)C * ((d->h_k[t] + G - 1) / G);
+        Mckp m(filler(t), ncls, nb, budget_bits);
+        choice[t].resize(ncls);
+        int rc = m.prepare_bound();
         double o = 0;
         int64_t u = 0;
-        int rc = inst[t]->exact(choice[t].data(), &o, &u);
+        if (rc == MGS_OK) rc = m.exact(choice[t].data(), &o, &u);
         st[t] = rc;
         if (rc == MGS_OK) {
             h_obj[t] = o;
@@ -818,7 +969,7 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
         const double best0 = h_obj[cand[0]];
         for (size_t i = 1; i < cand.size(); ++i) {
             const int t = cand[i];
-            if (inst[t]->lower_bound() <= best0 + inst[t]->tol + 1e-12 * std::fabs(best0))
+            if (lb[t] <= best0 + lbtol[t] + 1e-12 * std::fabs(best0))
                 todo.push_back(t);
             else
                 state[t] = MGS_SEARCH_PRUNED;

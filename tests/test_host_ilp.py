@@ -59,6 +59,42 @@ def test_vs_dp_medium(orc):
                 assert b[1] == a[1]
 
 
+def _rounding_broken_class(rng):
+    """Three options whose middle one stays on the lower hull (by the hull
+    test's products) while the two efficiencies, as quotients, rise along it:
+    near-collinear points where rounding decides.  Such a class makes the LP
+    step fall back from the sorted selection to the heap merge."""
+    while True:
+        sb = int(rng.integers(1, 51))
+        sc = sb + int(rng.integers(1, 51))
+        ea = 1.0 + float(rng.random())
+        slope = float(rng.random())
+        eb = ea - slope * sb * (1 + float(rng.choice([1e-16, -1e-16, 2e-16, -2e-16])))
+        ec = ea - slope * sc
+        if not ea > eb > ec or (eb - ea) * float(sc) >= (ec - ea) * float(sb):
+            continue
+        if (eb - ec) / float(sc - sb) > (ea - eb) / float(sb):
+            return [ea, eb, ec], [0, sb, sc]
+
+
+def test_rounding_broken_hull(orc):
+    rng = np.random.default_rng(17)
+    for trial in range(40):
+        ncls = int(rng.integers(2, 7)) if trial < 30 else int(rng.integers(20, 50))
+        err, size = rand_table(rng, ncls, 3, "mono")
+        for c in rng.choice(ncls, size=max(1, ncls // 2), replace=False):
+            err[c], size[c] = _rounding_broken_class(rng)
+        lo, hi = int(size.min(1).sum()), int(size.max(1).sum())
+        budget = int(rng.integers(lo, hi + 1))
+        a = orc.ilp_exhaustive(err, size, budget) if ncls <= 6 else orc.ilp_dp(err, size, budget)
+        b = mgs.ilp_solve(err, size, budget)
+        assert (a is None) == (b is None), trial
+        if a is not None:
+            assert b[1] == pytest.approx(a[1], rel=1e-12) and b[2] == a[2], (trial, a, b)
+            if b[0].tolist() != a[0].tolist():  # only possible on an exact tie
+                assert b[1] == a[1]
+
+
 def test_large_vs_highs():
     """Thousands of classes (the size of a real sweep's table) against HiGHS."""
     from scipy.optimize import LinearConstraint, milp
@@ -145,6 +181,49 @@ def test_search_vs_oracle(orc):
         assert res["best_t"] == best
         want = np.asarray(w.bits, np.uint8)[rows[best]["sol"][0]].reshape(w.channels, -1)
         assert np.array_equal(res["best_bits"], want)
+
+
+def test_search_rejects_invalid_tables():
+    """A loss that is not finite, or an entropy size that is negative or not
+    finite, fails the whole search, whether its ratio is solved, pruned or
+    skipped (its doubled all-8-bit size below the budget)."""
+    rng = np.random.default_rng(23)
+    N, C, G, bits = 4000, 3, 256, [2, 4, 8]
+    k = [400, 2000, 4000]
+    T, gm = len(k), (max(k) + G - 1) // G
+    err = np.sort(rng.uniform(0, 10, (T, C, gm, 3)), axis=3)[..., ::-1].copy()
+    bt = np.zeros((T, C, gm, 3))
+    for t, kt in enumerate(k):
+        for g in range((kt + G - 1) // G):
+            n = min(G, kt - g * G)
+            bt[t, :, g] = np.array(bits) * n * rng.uniform(0.3, 0.9, (C, 1))
+    ngs = [(kt + G - 1) // G for kt in k]
+    s8 = [int(np.ceil(bt[t, :, :ngs[t], 2]).sum()) + 72 * C * ngs[t] for t in range(T)]
+    budget = (s8[0] + s8[1]) // 2  # ratio 0 skipped (2 * s8 < budget), the others solved or pruned
+    assert 2 * s8[0] < budget <= 2 * s8[1]
+    ok = mgs.search(N, C, k, G, bits, err, bt, budget)
+    assert ok["status"][0] == mgs.SEARCH_SKIPPED and ok["best_t"] >= 1
+    for t in range(T):
+        for what in ("err_nan", "err_inf", "bits_neg", "bits_nan", "bits8_nan"):
+            e, b = err.copy(), bt.copy()
+            g = ngs[t] - 1
+            if what == "err_nan":
+                e[t, 1, g, 0] = np.nan
+            elif what == "err_inf":
+                e[t, 2, 0, 1] = np.inf
+            elif what == "bits_neg":
+                b[t, 0, g, 1] = -1.0
+            elif what == "bits_nan":
+                b[t, 2, g, 0] = np.nan
+            else:
+                b[t, 1, 0, 2] = np.nan
+            with pytest.raises(mgs.MgsError) as ex:
+                mgs.search(N, C, k, G, bits, e, b, budget)
+            assert ex.value.code == mgs.EINVAL, (t, what)
+        # linear sizes ignore the entropy table
+        b = bt.copy()
+        b[t, 0, 0, 0] = np.nan
+        mgs.search(N, C, k, G, bits, err, b, budget, size_mode=1)
 
 
 @pytest.mark.parametrize("kind", ["mono", "ties", "free"])
