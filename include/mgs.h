@@ -345,7 +345,7 @@ int mgs_graph_destroy(void* graph);
  * unless solved) and, if h_status is not NULL, h_status[t] (MGS_SEARCH_*).
  * Host work runs on up to `threads` threads (0 = all cores); each of them
  * keeps, between calls, the arrays of the largest LP bound it computed
- * (about 100 bytes per class and option).  Returns MGS_EINFEASIBLE when no
+ * (about 64 bytes per class and option).  Returns MGS_EINFEASIBLE when no
  * ratio is admissible, MGS_EINVAL when a loss is not finite or (size_mode 0)
  * an entropy size is negative or not finite, in any ratio.
  * ====================================================================== */
