@@ -886,9 +886,43 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
     std::vector<int> by_k(T);
     std::iota(by_k.begin(), by_k.end(), 0);
     std::stable_sort(by_k.begin(), by_k.end(), [&](int a, int b) { return d->h_k[a] > d->h_k[b]; });
+    // The smallest ratio that passes the doubled-8-bit test usually has the
+    // least bound, so it is solved at once, beside the other bounds; its
+    // result is used only where the ratio is solved anyway.
+    int t_spec = -1;
+    for (int i = T - 1; i >= 0 && t_spec < 0; --i) {
+        const int t = by_k[i];
+        const int64_t k = d->h_k[t], ng = (k + G - 1) / G;
+        int64_t s8 = 0;
+        bool ok = true;
+        for (int c = 0; c < C && ok; ++c)
+            for (int64_t g = 0; g < ng; ++g) {
+                const int64_t n = std::min<int64_t>(G, k - g * G);
+                if (b8 < 0 || size_mode == 1) {
+                    s8 += n * 8 + kMetaBits;
+                } else {
+                    const double b = h_bits[(((int64_t)t * C + c) * gmaxn + g) * nb + b8];
+                    if (!(std::isfinite(b) && b >= 0)) {
+                        ok = false;
+                        break;
+                    }
+                    s8 += (int64_t)std::ceil(b) + kMetaBits;
+                }
+            }
+        if (!ok) break;  // the pass below reports it
+        if (ng > 0 && 2 * s8 >= budget_bits) t_spec = t;
+    }
+    std::vector<int> items;
+    if (t_spec >= 0) items.push_back(t_spec);
+    for (int t : by_k)
+        if (t != t_spec) items.push_back(t);
+    std::vector<std::vector<uint8_t>> choice(T);
+    int spec_rc = MGS_EINVAL;  // the speculative solve: status, loss, size
+    double spec_obj = 0;
+    int64_t spec_used = 0;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
     for (int i = 0; i < T; ++i) {
-        const int t = by_k[i];
+        const int t = items[i];
         h_obj[t] = std::numeric_limits<double>::quiet_NaN();
         h_used[t] = 0;
         const int64_t k = d->h_k[t];
@@ -927,6 +961,19 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
             st[t] = MGS_EINVAL;
             continue;
         }
+        if (t == t_spec) {
+            Mckp m(filler(t), ncls, nb, budget_bits);
+            const int rc = m.prepare_bound();
+            if (rc == MGS_EINFEASIBLE) state[t] = MGS_SEARCH_INFEASIBLE;
+            else st[t] = rc;
+            lb[t] = m.lower_bound();
+            lbtol[t] = m.tol;
+            if (rc == MGS_OK) {
+                choice[t].resize(ncls);
+                spec_rc = m.exact(choice[t].data(), &spec_obj, &spec_used);
+            }
+            continue;
+        }
         static thread_local Mckp wk;
         wk.rebind(filler(t), ncls, nb, budget_bits);
         const int rc = wk.prepare_bound();
@@ -945,15 +992,21 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
     for (int t = 0; t < T; ++t)
         if (state[t] == MGS_SEARCH_SOLVED) cand.push_back(t);
     std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return lb[a] < lb[b]; });
-    std::vector<std::vector<uint8_t>> choice(T);
     auto solve_one = [&](int t) {
         const int64_t ncls = (int64_t)C * ((d->h_k[t] + G - 1) / G);
-        Mckp m(filler(t), ncls, nb, budget_bits);
-        choice[t].resize(ncls);
-        int rc = m.prepare_bound();
+        int rc = MGS_OK;
         double o = 0;
         int64_t u = 0;
-        if (rc == MGS_OK) rc = m.exact(choice[t].data(), &o, &u);
+        if (t == t_spec) {
+            rc = spec_rc;
+            o = spec_obj;
+            u = spec_used;
+        } else {
+            Mckp m(filler(t), ncls, nb, budget_bits);
+            choice[t].resize(ncls);
+            rc = m.prepare_bound();
+            if (rc == MGS_OK) rc = m.exact(choice[t].data(), &o, &u);
+        }
         st[t] = rc;
         if (rc == MGS_OK) {
             h_obj[t] = o;

@@ -199,10 +199,21 @@ def test_search_rejects_invalid_tables():
             bt[t, :, g] = np.array(bits) * n * rng.uniform(0.3, 0.9, (C, 1))
     ngs = [(kt + G - 1) // G for kt in k]
     s8 = [int(np.ceil(bt[t, :, :ngs[t], 2]).sum()) + 72 * C * ngs[t] for t in range(T)]
-    budget = (s8[0] + s8[1]) // 2  # ratio 0 skipped (2 * s8 < budget), the others solved or pruned
-    assert 2 * s8[0] < budget <= 2 * s8[1]
+    smin2 = int(np.ceil(bt[2, :, :ngs[2], 0]).sum()) + 72 * C * ngs[2]
+    budget = (smin2 + s8[1]) // 2  # ratio 0 skipped (2 * s8 < budget), the others feasible
+    assert 2 * s8[0] < budget <= 2 * s8[1] and smin2 <= budget
     ok = mgs.search(N, C, k, G, bits, err, bt, budget)
     assert ok["status"][0] == mgs.SEARCH_SKIPPED and ok["best_t"] >= 1
+    # the smallest admissible ratio (solved ahead of the others) made to lose:
+    # it is reported pruned, as any ratio whose bound exceeds the optimum
+    e = err.copy()
+    e[1] *= 100.0
+    fast = mgs.search(N, C, k, G, bits, e, bt, budget)
+    full = mgs.search(N, C, k, G, bits, e, bt, budget, solve_all=True)
+    assert fast["best_t"] == full["best_t"] == 2
+    assert fast["status"].tolist() == [mgs.SEARCH_SKIPPED, mgs.SEARCH_PRUNED, mgs.SEARCH_SOLVED]
+    assert np.isnan(fast["obj"][1]) and fast["used"][1] == 0
+    assert full["obj"][1] > full["obj"][2] and fast["obj"][2] == full["obj"][2]
     for t in range(T):
         for what in ("err_nan", "err_inf", "bits_neg", "bits_nan", "bits8_nan"):
             e, b = err.copy(), bt.copy()
