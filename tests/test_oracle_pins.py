@@ -538,3 +538,41 @@ def test_raht_invariants(orc):
     np.testing.assert_allclose(out[:, 0], math.sqrt(700) * a64.mean(1), rtol=1e-5)
     const = orc.raht_forward(coords, np.full((1, 700), 2.0, np.float32), 5)
     assert np.abs(const[0, 1:]).max() < 1e-5 and const[0, 0] == pytest.approx(2.0 * math.sqrt(700), rel=1e-6)
+
+
+def test_raht_depth2_by_hand(orc):
+    """A 3-D example two levels deep, worked by hand from T_1.  Six voxels of a
+    4 x 4 x 4 grid: p1 (0,0,0), p2 (1,0,0), p3 (0,1,0), p4 (1,0,1), p5 (3,2,0),
+    p6 (2,3,1).  Morton codes (x in bit 3l, y in bit 3l+1, z in bit 3l+2):
+    0, 1, 2, 5, 25, 30 -- the per-axis interleave (bit l + 2a) would give 0, 1,
+    4, 17, 11, 30 and z in bit 3l gives 0, 4, 2, 5, 52, 51: other orders.  Level 0, x: p1 + p2 (weights 1, 1); y: that
+    node (2) + p3 (1); z: that node (3) + p4 (1), and p5 + p6 (1, 1), which
+    meet only at this axis.  Level 1, x: nothing; y: the two nodes (4, 2).
+    Any other axis or level order changes the weights or the pairs, hence
+    these numbers."""
+    r2, r3, r6 = math.sqrt(2.0), math.sqrt(3.0), math.sqrt(6.0)
+    coords = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 0, 1], [3, 2, 0], [2, 3, 1]])
+    assert orc.morton(coords, 2).tolist() == [0, 1, 2, 5, 25, 30]
+    a = [1.0, 3.0, -2.0, 5.0, 0.5, 4.0]
+    l12 = (a[0] + a[1]) / r2
+    h1 = (a[1] - a[0]) / r2
+    l123 = (r2 * l12 + a[2]) / r3
+    h2 = (r2 * a[2] - l12) / r3
+    l1234 = (r3 * l123 + a[3]) / 2.0
+    h3 = (r3 * a[3] - l123) / 2.0
+    l56 = (a[4] + a[5]) / r2
+    h4 = (a[5] - a[4]) / r2
+    dc = (2.0 * l1234 + r2 * l56) / r6
+    h5 = (2.0 * l56 - r2 * l1234) / r6
+    want = [dc, h1, h2, h3, h4, h5]
+    # closed forms of the same numbers: the DC is sqrt(6) times the mean, and
+    # the first coefficients reduce to simple sums
+    assert dc == pytest.approx(sum(a) / r6, rel=1e-15)
+    assert h1 == pytest.approx(2.0 / r2, rel=1e-15)
+    assert h2 == pytest.approx((2.0 * -2.0 - 4.0) / r6, rel=1e-15)
+    assert h3 == pytest.approx((3.0 * 5.0 - 2.0) / (2.0 * r3), rel=1e-15)
+    attr = np.array([a, [2.0] * 6], np.float32)
+    out = orc.raht_forward(coords, attr, 2)
+    np.testing.assert_allclose(out[0], np.array(want, np.float32), rtol=2e-7, atol=1e-7)
+    # a constant channel: DC = 2 sqrt(6), every AC zero
+    np.testing.assert_allclose(out[1], [2.0 * r6, 0, 0, 0, 0, 0], atol=1e-6)
