@@ -53,6 +53,17 @@ def lib():
     return _LIB
 
 
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops for later calls from this thread
+    (libgomp's omp_set_num_threads); returns the number in effect before."""
+    lib()
+    gomp = ct.CDLL("libgomp.so.1")
+    gomp.omp_get_max_threads.restype = ct.c_int
+    before = int(gomp.omp_get_max_threads())
+    gomp.omp_set_num_threads(ct.c_int(int(n)))
+    return before
+
+
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ct.c_void_p)
 
