@@ -128,6 +128,34 @@ int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, const float
                     float* d_gmax, uint32_t* d_hist, void* d_ws, size_t ws_bytes, void* stream);
 
 /*
+ * Allocation-free sweep, for callers that cannot allocate device memory or
+ * hand over a workspace: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  mgs_quant_sweep_static computes exactly
+ * what mgs_quant_sweep computes (same kernels, launch shape and results) but
+ * keeps its scratch -- status word, scene descriptor, entropy tables, tile
+ * order -- in a device array of MGS_STATIC_SCRATCH_BYTES inside the library,
+ * one per GPU, held until the process ends.  Nothing is allocated, on the
+ * device or the host.  The caller still passes inputs and outputs as for
+ * mgs_quant_sweep.  Limit: the call returns MGS_EWORKSPACE (before touching
+ * the device) when mgs_quant_sweep_ws_bytes(desc) exceeds
+ * MGS_STATIC_SCRATCH_BYTES, i.e. for more than about 780,000 groups per
+ * channel run, sum_t ceil(k_t / G), at G = 65535 (more at smaller G).
+ * Every call on a GPU uses that GPU's one array and rewrites all of it
+ * (status word reset, tables and tile order rebuilt), so calls that overlap
+ * on one GPU -- on two streams, from two host threads, or a captured graph
+ * replayed beside another call -- race; calls on one stream in order do not.
+ * mgs_quant_sweep_static_status synchronises `stream` and returns the status
+ * word of the current GPU's array (MGS_ENONFINITE after a call that met a
+ * non-finite value, as mgs_status_fetch for a workspace).  Errors: as
+ * mgs_quant_sweep; MGS_EDEVICE if the array's address cannot be taken.
+ */
+#define MGS_STATIC_SCRATCH_BYTES (4 << 20)
+int mgs_quant_sweep_static(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                           const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                           float* d_gmax, uint32_t* d_hist, void* stream);
+int mgs_quant_sweep_static_status(void* stream);
+
+/*
  * Batched sweep: the sweeps of up to MGS_MAX_JOBS scenes (each with its own
  * N, C, reserve ratios, inputs and tables, all sharing G and the bit-width
  * list) in one launch; every table equals what mgs_quant_sweep computes for

@@ -790,9 +790,10 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
     // a b larger than a whole batch is split into windows of cap_words.
     // Scanned histograms with few bins get lane-interleaved copies (up to
     // REPL_WORDS words) so that lanes landing in one bin do not serialise on
-    // one LDS address.
+    // one LDS address.  Fixed-size arrays only: planning allocates nothing.
     struct Item { int bi; int words; bool packed; int rlog; };
-    std::vector<Item> items;
+    if (nb < 1 || nb > MGS_MAX_BITS) return false;
+    Item items[MGS_MAX_BITS];
     for (int i = 0; i < nb; ++i) {
         int full = 1 << bl[i];
         bool packed = full > cap_words;
@@ -800,15 +801,23 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         int rlog = 0;
         if (!packed && !rtn)
             while (rlog < REPL_MAX_LOG && (full << (rlog + 1)) <= std::min(REPL_WORDS, cap_words)) ++rlog;
-        items.push_back({i, packed ? full / 2 : full << rlog, packed, rlog});
+        // insertion keeps equal sizes in list order (a stable sort, largest first)
+        Item it{i, packed ? full / 2 : full << rlog, packed, rlog};
+        int pos = i;
+        while (pos > 0 && items[pos - 1].words < it.words) {
+            items[pos] = items[pos - 1];
+            --pos;
+        }
+        items[pos] = it;
     }
-    std::stable_sort(items.begin(), items.end(),
-                     [](const Item& a, const Item& c) { return a.words > c.words; });
-    std::vector<std::vector<HistEntry>> batches;
-    std::vector<int> used;
-    for (const Item& it : items) {
+    HistEntry bent[MGS_MAX_ENTRIES][MGS_MAX_ENTRIES];
+    int bcount[MGS_MAX_ENTRIES], used[MGS_MAX_ENTRIES];
+    int nbat = 0, ne = 0;
+    for (int ii = 0; ii < nb; ++ii) {
+        const Item& it = items[ii];
         if (it.words > cap_words) {
             for (int lo = 0; lo < it.words; lo += cap_words) {
+                if (nbat == MGS_MAX_ENTRIES || ne == MGS_MAX_ENTRIES) return false;
                 HistEntry e{};
                 e.bi = (int16_t)it.bi;
                 e.packed = it.packed;
@@ -818,18 +827,24 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
                 e.lo = lo;
                 e.nwords = std::min(cap_words, it.words - lo);
                 e.lds_off = 0;
-                batches.push_back({e});
-                used.push_back(e.nwords);
+                bent[nbat][0] = e;
+                bcount[nbat] = 1;
+                used[nbat] = e.nwords;
+                ++nbat;
+                ++ne;
             }
             continue;
         }
-        size_t k = 0;
-        for (; k < batches.size(); ++k)
+        int k = 0;
+        for (; k < nbat; ++k)
             if (used[k] + it.words <= cap_words) break;
-        if (k == batches.size()) {
-            batches.push_back({});
-            used.push_back(0);
+        if (k == nbat) {
+            if (nbat == MGS_MAX_ENTRIES) return false;
+            bcount[nbat] = 0;
+            used[nbat] = 0;
+            ++nbat;
         }
+        if (ne == MGS_MAX_ENTRIES) return false;
         HistEntry e{};
         e.bi = (int16_t)it.bi;
         e.packed = it.packed;
@@ -844,22 +859,20 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         e.nwords = it.words;
         e.lds_off = used[k];
         used[k] += it.words;
-        batches[k].push_back(e);
+        bent[k][bcount[k]++] = e;
+        ++ne;
     }
-    int ne = 0;
-    for (auto& b : batches) ne += (int)b.size();
-    if (ne > MGS_MAX_ENTRIES || (int)batches.size() > MGS_MAX_ENTRIES) return false;
-    p->nbatches = (int)batches.size();
+    p->nbatches = nbat;
     p->nentries = ne;
     p->max_batch_words = 0;
     int e = 0;
-    for (size_t k = 0; k < batches.size(); ++k) {
+    for (int k = 0; k < nbat; ++k) {
         p->batch_begin[k] = e;
         p->batch_words[k] = used[k];
         p->max_batch_words = std::max(p->max_batch_words, used[k]);
-        for (const HistEntry& he : batches[k]) p->entries[e++] = he;
+        for (int x = 0; x < bcount[k]; ++x) p->entries[e++] = bent[k][x];
     }
-    p->batch_begin[batches.size()] = e;
+    p->batch_begin[nbat] = e;
     return true;
 }
 
@@ -1132,6 +1145,57 @@ extern "C" int mgs_quant_sweep(const mgs_sweep_desc* desc, const float* d_attr, 
                                void* stream) {
     return sweep_launch(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, d_hist, d_ws,
                         ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+// ------------------------------------------------------------------ allocation-free form
+//
+// mgs_quant_sweep_static: the same launch as mgs_quant_sweep with the
+// workspace in a file-scope device array, for callers that cannot allocate.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it only stands for the symbol): the device address of each GPU's copy is
+// taken once per device with hipGetSymbolAddress and kept below.
+
+static __device__ __align__(256) unsigned char scratch[MGS_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each device (null until taken)
+}  // namespace
+
+// Device address of the current device's scratch array.
+static int static_scratch(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MGS_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MGS_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MGS_OK;
+}
+
+extern "C" int mgs_quant_sweep_static(const mgs_sweep_desc* desc, const float* d_attr, const float* d_imp,
+                                      const int32_t* d_kept, double* d_err, double* d_bits, float* d_gmin,
+                                      float* d_gmax, uint32_t* d_hist, void* stream) {
+    mgs::SceneDesc sc;
+    int rc = mgs::fill_scene(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, d_hist, &sc);
+    if (rc) return rc;
+    // the workspace this launch needs must fit in the array (checked before any HIP call)
+    if (sweep_ws_bytes(1, sc.G, sc.gpc) > (size_t)MGS_STATIC_SCRATCH_BYTES) return MGS_EWORKSPACE;
+    void* ws = nullptr;
+    rc = static_scratch(&ws);
+    if (rc) return rc;
+    return sweep_launch_scenes(&sc, 1, ws, (size_t)MGS_STATIC_SCRATCH_BYTES, (hipStream_t)stream, nullptr);
+}
+
+extern "C" int mgs_quant_sweep_static_status(void* stream) {
+    void* ws = nullptr;
+    int rc = static_scratch(&ws);
+    if (rc) return rc;
+    return mgs_status_fetch(ws, stream);
 }
 
 extern "C" int mgs_quant_sweep_multi(const mgs_sweep_job* h_jobs, int32_t njobs, void* d_ws,

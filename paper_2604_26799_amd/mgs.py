@@ -49,6 +49,8 @@ SIGNATURES = {
     "mgs_prune_select": (ct.c_int, [P, I64, P, I32, P, P, SZ, P]),
     "mgs_quant_sweep_ws_bytes": (SZ, [P]),
     "mgs_quant_sweep": (ct.c_int, [P, P, P, P, P, P, P, P, P, P, SZ, P]),
+    "mgs_quant_sweep_static": (ct.c_int, [P, P, P, P, P, P, P, P, P, P]),
+    "mgs_quant_sweep_static_status": (ct.c_int, [P]),
     "mgs_quant_sweep_multi_ws_bytes": (SZ, [P, I32]),
     "mgs_quant_sweep_multi": (ct.c_int, [P, I32, P, SZ, P]),
     "mgs_sweep_shape_count": (ct.c_int, []),
@@ -199,6 +201,23 @@ def quant_sweep(attr, imp, kept, k, G: int, bits, want_hist: bool = False, ws=No
                                  _dptr(out["gmax"]), _dptr(out["hist"]), _dptr(ws), ws.numel(),
                                  _stream(stream)), "mgs_quant_sweep")
     _finish(ws, check, "mgs_quant_sweep", stream)
+    return out
+
+
+def quant_sweep_static(attr, imp, kept, k, G: int, bits, out=None, stream=None, check: bool = True):
+    """The sweep without a workspace (the library's per-GPU scratch array);
+    same tables as ``quant_sweep``."""
+    C, N = attr.shape
+    d = sweep_desc(N, C, k, G, bits)
+    if out is None:
+        hb = 0
+        out = sweep_tables(d.T, C, gmax_groups(k, G), d.nb, attr.device, hb)
+    _check(lib().mgs_quant_sweep_static(ct.byref(d), _dptr(attr), _dptr(imp), _dptr(kept) if kept.numel() else None,
+                                        _dptr(out["err"]), _dptr(out["bits"]), _dptr(out["gmin"]),
+                                        _dptr(out["gmax"]), _dptr(out.get("hist")), _stream(stream)),
+           "mgs_quant_sweep_static")
+    if check:
+        _check(lib().mgs_quant_sweep_static_status(_stream(stream)), "mgs_quant_sweep_static")
     return out
 
 

@@ -187,3 +187,27 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and not r.stdout
+
+
+def test_static_sweep_rejects_before_the_device():
+    """The allocation-free sweep checks its arguments and its scratch limit
+    on the host: a bad descriptor is EINVAL, a launch whose workspace would
+    exceed MGS_STATIC_SCRATCH_BYTES (4 MiB; 785,920 groups per channel run at
+    G = 65535) is EWORKSPACE -- both without touching a device."""
+    L = mgs.lib()
+    fake = ct.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+    def call(N, C, k, G, bits):
+        d = mgs.sweep_desc(N, C, k, G, bits)
+        return L.mgs_quant_sweep_static(ct.byref(d), fake, fake, fake, fake, fake, fake, fake, None, None)
+
+    assert call(100, 2, [50, 100], 0, [2, 4]) == mgs.EINVAL
+    assert call(100, 2, [101], 16, [2, 4]) == mgs.EINVAL
+    assert call(1_000_000, 2, [1_000_000] * 4, 1, [2, 4]) == mgs.EWORKSPACE
+    # the limit is the workspace query against 4 MiB
+    for G, groups in ((65535, 785_920), (8192, 1_015_232)):
+        for g, fits in ((groups, True), (groups + 1, False)):
+            d = mgs.sweep_desc(g * G, 1, [g * G], G, [2])
+            assert (L.mgs_quant_sweep_ws_bytes(ct.byref(d)) <= 4 << 20) == fits
+    d = mgs.sweep_desc(785_921 * 65535 // 32, 1, [785_921 * 65535 // 32] * 32, 65535, [2])
+    assert L.mgs_quant_sweep_static(ct.byref(d), fake, fake, fake, fake, fake, fake, fake, None, None) == mgs.EWORKSPACE
