@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=64,
                     help="jobs of the served stream (Poisson 2/s); 0 skips the served form")
-    ap.add_argument("--overlap-rate", type=float, default=50.0,
+    ap.add_argument("--overlap-rate", type=float, default=100.0,
                     help="arrival rate (jobs/s) of the second served stream, where arrivals overlap")
     ap.add_argument("--no-medium", action="store_true", help="skip the medium-workload sweep leg")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time of the CPU baseline")
@@ -409,10 +409,28 @@ def raht_timing(mgs, torch, w, attr_h, s, depth: int = 14, reps: int = 3):
         back = mgs.raht(cd, coef, depth, inverse=True, ws=ws, stream=s, check=False)
     e[2].record(s)
     e[2].synchronize()
+    fwd_ms, inv_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
     err = float((back - a).abs().max())
+    # the sweep over the AC coefficients (DC kept in floating point, unit weights)
+    kept = torch.arange(1, n, dtype=torch.int32, device=a.device)
+    ones = torch.ones(n, dtype=torch.float32, device=a.device)
+    import ctypes as ct
+    d = mgs.sweep_desc(n, C, [n - 1], w.group, w.bits)
+    wss = mgs.workspace(mgs.lib().mgs_quant_sweep_ws_bytes(ct.byref(d)), a.device)
+    tab = mgs.sweep_tables(1, C, mgs.gmax_groups([n - 1], w.group), len(w.bits), a.device)
+    mgs.quant_sweep(coef, ones, kept, [n - 1], w.group, w.bits, ws=wss, out=tab, stream=s)
+    e[0].record(s)
+    for _ in range(reps):
+        mgs.quant_sweep(coef, ones, kept, [n - 1], w.group, w.bits, ws=wss, out=tab, stream=s, check=False)
+    e[1].record(s)
+    e[1].synchronize()
+    ac_ms = e[0].elapsed_time(e[1]) / reps
+    ac_evals = (n - 1) * C * len(w.bits)
     return {"points": n, "channels": C, "depth": depth, "steps": 3 * depth,
-            "forward_ms": e[0].elapsed_time(e[1]) / reps, "inverse_ms": e[1].elapsed_time(e[2]) / reps,
-            "roundtrip_max_abs_err": err}
+            "forward_ms": fwd_ms, "inverse_ms": inv_ms,
+            "roundtrip_max_abs_err": err,
+            "ac_sweep": {"ms": ac_ms, "evals": ac_evals, "evals_per_s": ac_evals / (ac_ms * 1e-3),
+                         "G": w.group, "bits": f"{w.bits[0]}..{w.bits[-1]}"}}
 
 
 def kmeans_iterations(mgs, torch, x, cb, s, batch_rows: int = 1 << 18, iters: int = 5):

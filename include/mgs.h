@@ -183,16 +183,22 @@ int mgs_quant_sweep_multi(const mgs_sweep_job* h_jobs, int32_t njobs, void* d_ws
                           void* stream);
 
 /*
- * Launch shape of the sweep kernel (threads per workgroup, elements per
+ * Launch shape of the sweep kernel: threads per workgroup, elements per
  * thread, LDS bytes the histogram plan may use (0 = the device maximum),
- * channels per workgroup tile (0 = all channels)).
+ * channels per workgroup tile (0 = all channels), and the grid: 0 = one
+ * workgroup per tile, 1 = persistent (one workgroup per resident slot of the
+ * device, taking tiles in order from one counter per XCD and then from the
+ * other XCDs' counters; the counters live in the workspace's status block
+ * and are reset by every call, so the launch stays graph-capturable).
  * mgs_sweep_autotune times every candidate shape on the given inputs (each
  * `reps` times, HIP events on `stream`, minimum kept), registers the fastest
- * for (G, nb, max bit-width) in a process-wide table used by later sweeps,
- * and leaves the tables computed with it.  It synchronises the stream, so it
- * must not be called during graph capture.  h_ms[i] / h_shapes[i][4]
+ * for (G, nb, max bit-width) in a process-wide table used by later sweeps --
+ * among shapes within 3 % of the fastest, the one with more channels per
+ * tile, which fetches each tile's indices and weights fewer times -- and
+ * leaves the tables computed with it.  It synchronises the stream, so it
+ * must not be called during graph capture.  h_ms[i] / h_shapes[i][5]
  * (optional, mgs_sweep_shape_count() entries) receive each candidate's time
- * (-1 when it does not apply) and shape; h_best[4] (optional) the chosen one.
+ * (-1 when it does not apply) and shape; h_best[5] (optional) the chosen one.
  * mgs_sweep_set_shape registers a shape by hand (nt == 0 clears the entry).
  * Results are identical for every shape.
  */
@@ -202,7 +208,7 @@ int mgs_sweep_autotune(const mgs_sweep_desc* desc, const float* d_attr, const fl
                        float* d_gmax, void* d_ws, size_t ws_bytes, void* stream, int32_t reps,
                        float* h_ms, int32_t* h_shapes, int32_t* h_best);
 int mgs_sweep_set_shape(int32_t G, int32_t nb, int32_t bmax, int32_t nt, int32_t ept,
-                        int32_t lds_cap, int32_t cpb);
+                        int32_t lds_cap, int32_t cpb, int32_t persist);
 
 /* ======================================================================
  * Final quantization at a chosen bit allocation, and its inverse (paper:
@@ -259,8 +265,10 @@ int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float* d_cb, int
  *   c_j <- (v_j c_j + sum of its batch rows) / (v_j + n_j)   (FP64, stored FP32)
  * and d_counts[j] += n_j.  Sculley's per-sample update (eta = 1 / v) reaches
  * the same mean.  d_cb and d_counts are updated in place (centers with no
- * rows keep their value).  The FP64 sums are atomic, so the mean is
- * reproducible to about B * 2^-53 relative before the FP32 rounding.
+ * rows keep their value).  The sum of a center's rows is taken in FP64 one
+ * row after another in batch order (the rows are grouped by center with a
+ * stable sort), then (v_j c_j + sum) / (v_j + n_j) in FP64, stored as FP32:
+ * the same inputs give bit-identical centers on every run.
  * Workspace: mgs_kmeans_step_ws_bytes(B, D, K).  Errors: MGS_EINVAL
  * (N < 0, B outside [0, 2^31), D outside [1, MGS_MAX_VQ_DIM], K outside [1, 2^30], NULL
  * pointers), MGS_EWORKSPACE; non-finite rows or centers, and batch indices

@@ -365,6 +365,37 @@ def kmeans_step(x, cb, counts, batch):
     return c.astype(np.float32), v, assign
 
 
+def kmeans_step_batched(x, cb, counts, batch):
+    """The same iteration in the batched form of the running mean (section
+    "Attribute Transformation", paragraph "Clustering 1+D SH Coefficients"):
+    the batch rows are assigned to their nearest center (``vq_assign``), then
+    every center j with n_j > 0 rows moves to
+        c_j <- (v_j c_j + S_j) / (v_j + n_j),   v_j += n_j,
+    where S_j is the FP64 sum of its rows taken one after another in batch
+    order, and the products, sums and quotient are single FP64 operations in
+    that order; the center is stored as FP32.  Returns (centers f32 [K][D],
+    counts i64 [K], assignment i32 [B])."""
+    x = np.asarray(x, dtype=np.float32)
+    cb = np.asarray(cb, dtype=np.float32)
+    batch = np.asarray(batch, dtype=np.int64)
+    rows = x[batch]
+    assign, _ = vq_assign(np.ascontiguousarray(rows), cb)
+    out = cb.copy()
+    v = np.array(counts, dtype=np.int64).copy()
+    for j in range(cb.shape[0]):
+        mine = rows[assign == j].astype(np.float64)
+        n = mine.shape[0]
+        if n == 0:
+            continue
+        total = np.zeros(cb.shape[1], dtype=np.float64)
+        for r in range(n):           # one row after another, in batch order
+            total = total + mine[r]
+        vj = np.float64(v[j])
+        out[j] = ((vj * cb[j].astype(np.float64) + total) / np.float64(v[j] + n)).astype(np.float32)
+        v[j] += n
+    return out, v, assign
+
+
 def vq_retain(x, imp, cb, idx, remaining_bits: int):
     """Budget-first retention (same paragraph of the paper): with the bits
     left after the essential components, keep the original vectors of the

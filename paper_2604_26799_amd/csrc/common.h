@@ -11,7 +11,9 @@
 // Status word layout at the start of every workspace.
 struct mgs_status_block {
     uint32_t nonfinite;
-    uint32_t pad[63];
+    uint32_t pad0[15];
+    uint32_t queue[16];  // tile counters of a persistent launch (one per XCD), reset with the status
+    uint32_t pad[32];
 };
 static constexpr size_t MGS_STATUS_BYTES = sizeof(mgs_status_block);  // 256
 

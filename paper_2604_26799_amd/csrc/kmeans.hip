@@ -11,11 +11,15 @@
 //      of this batch, moves to the running mean of all of them:
 //        c_j <- (v_j c_j + sum of its batch rows) / (v_j + n_j),  v_j += n_j.
 // Sculley's per-sample update (v += 1, eta = 1 / v, c <- (1 - eta) c + eta x,
-// applied to the batch's rows in order) reaches the same mean; the batched
-// form needs no order.  Sums are FP64 atomics into the workspace (their order
-// varies, so the FP64 mean is reproducible to about B * 2^-53 relative), the
-// result is rounded to FP32 once.
+// applied to the batch's rows in order) reaches the same mean.  The sum of a
+// center's rows is taken in FP64 in batch order: the batch positions are
+// sorted by center with a stable radix sort (rocPRIM), so each center's rows
+// form one run in batch order, and one wave per center adds its run
+// sequentially (lane d adds dimension d).  The result, rounded to FP32 once,
+// is therefore the same on every run, bit for bit.
 #include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
 
@@ -27,8 +31,10 @@ struct KmArgs {
     const int64_t* batch;
     float* xb;          // [B][D] gathered batch rows
     int32_t* assign;    // [B]
-    double* sums;       // [K][D]
-    int64_t* nb;        // [K] rows of this batch per center
+    uint32_t* keys;     // [B] sort keys: the center, K for rows without one
+    uint32_t* keys_s;   // [B] the keys sorted
+    int32_t* pos;       // [B] batch positions 0 .. B-1
+    int32_t* pos_s;     // [B] batch positions in center order (stable: batch order within a center)
     float* cb;          // [K][D] centers (in place)
     int64_t* counts;    // [K] samples absorbed so far
     mgs_status_block* status;
@@ -52,31 +58,60 @@ __global__ void km_gather_kernel(KmArgs a) {
     }
 }
 
-// Per-center FP64 sums and counts of the batch rows.
-__global__ void km_accumulate_kernel(KmArgs a) {
-    const int64_t total = a.B * a.D;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = i / a.D;
-        const int d = (int)(i - r * a.D);
+// Sort keys and batch positions of the batch rows.
+__global__ void km_keys_kernel(KmArgs a) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < a.B;
+         r += (int64_t)gridDim.x * blockDim.x) {
         const int j = a.assign[r];
-        if ((unsigned)j >= (unsigned)a.K) continue;  // rows the assignment flagged non-finite
-        atomicAdd(&a.sums[(int64_t)j * a.D + d], (double)a.xb[i]);
-        if (d == 0) atomicAdd((unsigned long long*)&a.nb[j], 1ull);
+        a.keys[r] = (unsigned)j < (unsigned)a.K ? (uint32_t)j : (uint32_t)a.K;
+        a.pos[r] = (int32_t)r;
     }
 }
 
-// The running-mean update of every center that received rows.
-__global__ void km_update_kernel(KmArgs a) {
-    const int64_t total = (int64_t)a.K * a.D;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = i / a.D;
-        const int64_t n = a.nb[j];
+// First index of the sorted keys that is >= key.
+__device__ __forceinline__ int64_t lower_bound_u32(const uint32_t* k, int64_t n, uint32_t key) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (k[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One wave per center: the run of its rows in the sorted order, summed in
+// batch order in FP64 (lane d: dimension d), then the running-mean update
+// c <- (v c + sum) / (v + n) and v += n.  Centers without rows keep their
+// value and count.
+__global__ void km_center_kernel(KmArgs a) {
+    const int lane = threadIdx.x & (MGS_WAVE - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / MGS_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / MGS_WAVE;
+    for (int64_t j = wave; j < a.K; j += nwaves) {
+        const int64_t lo = lower_bound_u32(a.keys_s, a.B, (uint32_t)j);
+        const int64_t hi = lower_bound_u32(a.keys_s, a.B, (uint32_t)j + 1u);
+        const int64_t n = hi - lo;
         if (n == 0) continue;
         const int64_t v = a.counts[j];
-        const double c = (double)a.cb[i];
-        a.cb[i] = (float)(((double)v * c + a.sums[i]) / (double)(v + n));
+        if (lane < a.D) {
+            const float* xd = a.xb + lane;
+            double s = 0.0;
+            int64_t i = lo;
+            for (; i + 4 <= hi; i += 4) {  // four rows' loads in flight, added in order
+                const float v0 = xd[(int64_t)a.pos_s[i] * a.D];
+                const float v1 = xd[(int64_t)a.pos_s[i + 1] * a.D];
+                const float v2 = xd[(int64_t)a.pos_s[i + 2] * a.D];
+                const float v3 = xd[(int64_t)a.pos_s[i + 3] * a.D];
+                s += (double)v0;
+                s += (double)v1;
+                s += (double)v2;
+                s += (double)v3;
+            }
+            for (; i < hi; ++i) s += (double)xd[(int64_t)a.pos_s[i] * a.D];
+            float* c = a.cb + j * a.D + lane;
+            *c = (float)(((double)v * (double)*c + s) / (double)(v + n));
+        }
+        if (lane == 0) a.counts[j] = v + n;
     }
 }
 
@@ -85,28 +120,40 @@ __global__ void km_status_kernel(const mgs_status_block* vq, mgs_status_block* o
     if (threadIdx.x == 0 && vq->nonfinite) atomicOr(&own->nonfinite, vq->nonfinite);
 }
 
-// The absorbed-sample counts, after every value of the center is updated.
-__global__ void km_counts_kernel(KmArgs a) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.K;
-         j += (int64_t)gridDim.x * blockDim.x)
-        a.counts[j] += a.nb[j];
-}
-
 struct KmLayout {
-    size_t xb, assign, sums, nb, vq, total;
+    size_t xb, assign, keys, keys_s, pos, pos_s, sort, sort_bytes, vq, total;
 };
+
+// Key bits of the sort: enough for the keys 0 .. K (K marks rows without a center).
+int km_key_bits(int32_t K) {
+    int bits = 1;
+    while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)K) ++bits;
+    return bits;
+}
 
 KmLayout km_layout(int64_t B, int32_t D, int32_t K) {
     KmLayout L;
+    const size_t b = (size_t)std::max<int64_t>(B, 1);
     size_t o = MGS_STATUS_BYTES;
     L.xb = o;
-    o += mgs_align_up(sizeof(float) * (size_t)std::max<int64_t>(B, 1) * D, 256);
+    o += mgs_align_up(sizeof(float) * b * D, 256);
     L.assign = o;
-    o += mgs_align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(B, 1), 256);
-    L.sums = o;
-    o += mgs_align_up(sizeof(double) * (size_t)K * D, 256);
-    L.nb = o;
-    o += mgs_align_up(sizeof(int64_t) * (size_t)K, 256);
+    o += mgs_align_up(sizeof(int32_t) * b, 256);
+    L.keys = o;
+    o += mgs_align_up(sizeof(uint32_t) * b, 256);
+    L.keys_s = o;
+    o += mgs_align_up(sizeof(uint32_t) * b, 256);
+    L.pos = o;
+    o += mgs_align_up(sizeof(int32_t) * b, 256);
+    L.pos_s = o;
+    o += mgs_align_up(sizeof(int32_t) * b, 256);
+    // temporary storage of the radix sort (a size query: no device work)
+    L.sort_bytes = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, L.sort_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                    (const int32_t*)nullptr, (int32_t*)nullptr, (unsigned)b, 0,
+                                    km_key_bits(K));
+    L.sort = o;
+    o += mgs_align_up(std::max<size_t>(L.sort_bytes, 1), 256);
     L.vq = o;
     o += mgs_align_up(mgs_vq_assign_ws_bytes(B, D, K), 256);
     L.total = o;
@@ -145,8 +192,10 @@ extern "C" int mgs_kmeans_step(const float* d_x, int64_t N, int32_t D, const int
     a.batch = d_batch;
     a.xb = (float*)(ws + L.xb);
     a.assign = d_assign ? d_assign : (int32_t*)(ws + L.assign);
-    a.sums = (double*)(ws + L.sums);
-    a.nb = (int64_t*)(ws + L.nb);
+    a.keys = (uint32_t*)(ws + L.keys);
+    a.keys_s = (uint32_t*)(ws + L.keys_s);
+    a.pos = (int32_t*)(ws + L.pos);
+    a.pos_s = (int32_t*)(ws + L.pos_s);
     a.cb = d_cb;
     a.counts = d_counts;
     a.status = (mgs_status_block*)ws;
@@ -157,9 +206,6 @@ extern "C" int mgs_kmeans_step(const float* d_x, int64_t N, int32_t D, const int
     int rc = mgs_fill<uint32_t>((uint32_t*)ws, 64, 0u, s);
     if (rc) return rc;
     if (B == 0) return MGS_OK;
-    rc = mgs_fill<double>(a.sums, (int64_t)K * D, 0.0, s);
-    if (!rc) rc = mgs_fill<int64_t>(a.nb, K, (int64_t)0, s);
-    if (rc) return rc;
     hipLaunchKernelGGL(km_gather_kernel, dim3(km_blocks(B * D)), dim3(256), 0, s, a);
     rc = mgs_last_launch();
     if (rc) return rc;
@@ -170,9 +216,18 @@ extern "C" int mgs_kmeans_step(const float* d_x, int64_t N, int32_t D, const int
                        mgs_vq_assign_ws_bytes(B, D, K), stream);
     if (rc) return rc;
     hipLaunchKernelGGL(km_status_kernel, dim3(1), dim3(64), 0, s, (const mgs_status_block*)vq_ws, a.status);
-    hipLaunchKernelGGL(km_accumulate_kernel, dim3(km_blocks(B * D)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(km_update_kernel, dim3(km_blocks((int64_t)K * D)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(km_counts_kernel, dim3(km_blocks(K)), dim3(256), 0, s, a);
+    // the batch positions grouped by center, batch order kept within a center
+    hipLaunchKernelGGL(km_keys_kernel, dim3(km_blocks(B)), dim3(256), 0, s, a);
+    rc = mgs_last_launch();
+    if (rc) return rc;
+    size_t sort_bytes = L.sort_bytes;
+    if (rocprim::radix_sort_pairs((void*)(ws + L.sort), sort_bytes, (const uint32_t*)a.keys, a.keys_s,
+                                  (const int32_t*)a.pos, a.pos_s, (unsigned)B, 0, km_key_bits(K), s) !=
+        hipSuccess)
+        return MGS_EDEVICE;
+    // one wave per center (grid-stride over the centers)
+    const int64_t waves = std::min<int64_t>(K, 1 << 16);
+    hipLaunchKernelGGL(km_center_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a);
     return mgs_last_launch();
 }
 

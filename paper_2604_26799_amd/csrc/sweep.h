@@ -64,6 +64,7 @@ struct SweepParams {
     int32_t cpb;              // channels per tile
     int32_t nbatches, nentries, max_batch_words;
     int32_t kgrid;            // K of the increment grid
+    int32_t persist;          // persistent grid: tiles from the per-XCD counters of status->queue
     int32_t batch_begin[MGS_MAX_ENTRIES + 1];
     int32_t batch_words[MGS_MAX_ENTRIES];
     HistEntry entries[MGS_MAX_ENTRIES];
@@ -75,6 +76,7 @@ struct Shape {
     int ept;       // elements per thread (nt * ept >= G, else the chunked kernel)
     int lds_cap;   // LDS bytes the histogram plan may use (0 = device maximum)
     int cpb = 0;   // channels per tile (0 = all channels)
+    int persist = 0;  // 1: a persistent grid sized to the resident slots, tiles from per-XCD queues
 };
 
 int fill_scene(const mgs_sweep_desc* d, const float* attr, const float* imp, const int32_t* kept,

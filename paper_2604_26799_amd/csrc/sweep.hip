@@ -286,6 +286,55 @@ __device__ __forceinline__ Part eval_fast_dispatch(bool check, bool rtn, bool wi
 #undef MGS_EVAL
 }
 
+// Sum of v over each group of 2^rl adjacent lanes (rl <= 5), in the group's
+// last lane: a sliding window built from DPP row shifts (lanes shifted in
+// from outside the row read 0), then, for groups of 32, the row's window
+// plus the previous row's (row broadcast of lane 15).  Other lanes hold
+// partial sums.  Called by all lanes of a wave.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true);
+}
+__device__ __forceinline__ uint32_t group_sum_u32(uint32_t v, int rl) {
+    if (rl >= 1) v += dpp_u32<0x111, 0xF>(v);  // row_shr:1
+    if (rl >= 2) v += dpp_u32<0x112, 0xF>(v);  // row_shr:2
+    if (rl >= 3) v += dpp_u32<0x114, 0xF>(v);  // row_shr:4
+    if (rl >= 4) v += dpp_u32<0x118, 0xF>(v);  // row_shr:8
+    if (rl >= 5) v += dpp_u32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    return v;
+}
+
+// Wavefront min / max / OR by DPP row shifts and row broadcasts (lanes whose
+// source lies outside the row, or rows the mask leaves out, take the
+// identity); the result is read from lane 63, so every lane gets it.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_keep(uint32_t v, uint32_t ident) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+template <typename F>
+__device__ __forceinline__ uint32_t wave_reduce_dpp(uint32_t v, uint32_t ident, F op) {
+    v = op(v, dpp_keep<0x111, 0xF>(v, ident));
+    v = op(v, dpp_keep<0x112, 0xF>(v, ident));
+    v = op(v, dpp_keep<0x114, 0xF>(v, ident));
+    v = op(v, dpp_keep<0x118, 0xF>(v, ident));
+    v = op(v, dpp_keep<0x142, 0xA>(v, ident));
+    v = op(v, dpp_keep<0x143, 0xC>(v, ident));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ float wave_min_dpp(float v) {
+    return __uint_as_float(wave_reduce_dpp(__float_as_uint(v), __float_as_uint(INFINITY), [](uint32_t a, uint32_t b) {
+        return __float_as_uint(fminf(__uint_as_float(a), __uint_as_float(b)));
+    }));
+}
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    return __uint_as_float(wave_reduce_dpp(__float_as_uint(v), __float_as_uint(-INFINITY), [](uint32_t a, uint32_t b) {
+        return __float_as_uint(fmaxf(__uint_as_float(a), __uint_as_float(b)));
+    }));
+}
+__device__ __forceinline__ uint32_t wave_or_dpp(uint32_t v) {
+    return wave_reduce_dpp(v, 0u, [](uint32_t a, uint32_t b) { return a | b; });
+}
+
 // Waves per SIMD the register budget must allow: <= 128 VGPRs for shapes
 // that hold 16 or fewer elements per thread, so that two 512-thread blocks
 // (or four of 256) share a CU when their histograms fit in LDS.
@@ -296,7 +345,7 @@ template <int NT, int EPT, bool CHUNKED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<NT, EPT, CHUNKED>())))
 void sweep_kernel(SweepParams p) {
     constexpr int NW = NT / MGS_WAVE;
-    extern __shared__ uint32_t hist[];
+    extern __shared__ __align__(16) uint32_t hist[];  // 16-byte aligned: cleared and read as uint4
     __shared__ double lg[LGTAB];
     __shared__ double lf[LGTAB];
     __shared__ double errpart[MGS_MAX_BITS][NW];
@@ -320,19 +369,53 @@ void sweep_kernel(SweepParams p) {
     // up to (only counts above LGTAB need it)
     const double rt_cycle = p.lgtab_max >= LGTAB ? grid_round(lgt[LGTAB], p.kgrid) : 0.0;
 
-    // Workgroups are dispatched round-robin over the XCDs: give each XCD a
+    // Workgroups are dispatched round-robin over the XCDs: each XCD gets a
     // contiguous run of tiles, so that one XCD's L2 serves the neighbouring
-    // groups of every ratio (a grid that is not a multiple of the XCD count
-    // strides plainly).
+    // groups of every ratio.  A grid of one workgroup per tile strides over
+    // its run (a grid that is not a multiple of the XCD count strides
+    // plainly).  A persistent grid (p.persist: about one workgroup per
+    // resident slot) takes tiles from a counter per run, in order, and when
+    // its own XCD's run is drained moves on to the other runs; every counter
+    // only grows, so each workgroup leaves once all runs are drained.
+    const int64_t per = (p.ntiles + MGS_XCDS - 1) / MGS_XCDS;
     int64_t it0 = blockIdx.x, step = gridDim.x, it_end = p.ntiles;
     if (gridDim.x % MGS_XCDS == 0) {
-        const int64_t per = (p.ntiles + MGS_XCDS - 1) / MGS_XCDS;
         const int x = (int)(blockIdx.x % MGS_XCDS);
         it0 = (int64_t)x * per + blockIdx.x / MGS_XCDS;
         step = gridDim.x / MGS_XCDS;
         it_end = min(p.ntiles, (int64_t)(x + 1) * per);
     }
-    for (int64_t it = it0; it < it_end; it += step) {
+    __shared__ int64_t grabbed;
+    const int qx0 = (int)(blockIdx.x % MGS_XCDS);
+    int qk = 0;
+    for (int64_t it = it0 - step;;) {
+        if (p.persist) {
+            bool got = false;
+            while (qk < MGS_XCDS) {
+                const int x = (qx0 + qk) % MGS_XCDS;
+                const int64_t hi = min(p.ntiles, (int64_t)(x + 1) * per);
+                if (tid == 0)
+                    grabbed = (int64_t)x * per +
+                              (int64_t)__hip_atomic_fetch_add(&p.status->queue[x], 1u, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                {  // the same value in every lane: keep it (and all that derives from it) scalar
+                    const int64_t g = grabbed;
+                    it = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(g >> 32)) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readfirstlane((int)g));
+                }
+                __syncthreads();  // every thread has read it before the next grab
+                if (it < hi) {
+                    got = true;
+                    break;
+                }
+                ++qk;
+            }
+            if (!got) break;
+        } else {
+            it += step;
+            if (it >= it_end) break;
+        }
         // ---- locate the tile: scene, then (channel run, ratio t, group g)
         // with the run's groups taken in the scene's tile order; channels
         // [c0, c1)
@@ -400,10 +483,10 @@ void sweep_kernel(SweepParams p) {
             } else {
                 gather(0);
             }
-            mn = wave_min_f32(mn);
-            mx = wave_max_f32(mx);
-            wm = wave_max_f32(wm);
-            bad = wave_or_u32(bad);
+            mn = wave_min_dpp(mn);
+            mx = wave_max_dpp(mx);
+            wm = wave_max_dpp(wm);
+            bad = wave_or_dpp(bad);
             if (lane == 0) {
                 red_mn[wave] = mn;
                 red_mx[wave] = mx;
@@ -584,13 +667,14 @@ void sweep_kernel(SweepParams p) {
                     };
                     if (en.rlog) {
                         // replicated bins: the 2^rlog copies of a bin sit in adjacent
-                        // lanes of one wavefront; a butterfly sums them
+                        // lanes of one wavefront; DPP row shifts sum them into the
+                        // group's last lane
                         const int rl = en.rlog, R = 1 << rl;
                         for (int w0 = 0; w0 < en.nwords; w0 += NT) {
                             const int w = w0 + tid;
-                            uint32_t h = w < en.nwords ? hist[en.lds_off + w] : 0u;
-                            for (int o = 1; o < R; o <<= 1) h += (uint32_t)__shfl_xor((int)h, o, MGS_WAVE);
-                            if ((lane & (R - 1)) == 0 && w < en.nwords) {
+                            const uint32_t h =
+                                group_sum_u32(w < en.nwords ? hist[en.lds_off + w] : 0u, rl);
+                            if ((lane & (R - 1)) == R - 1 && w < en.nwords) {
                                 term(h);
                                 if (hout) hout[en.lo + (w >> rl)] = h;
                             }
@@ -677,7 +761,10 @@ __device__ void tile_order(SceneDesc* sc, int r) {
 // cleared; the status word is reset; every scene gets its tile order.
 __global__ void sweep_init_kernel(SceneDesc* __restrict__ scenes, int count,
                                   mgs_status_block* status, double* lgtab, int lgtab_max, int K) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) status->nonfinite = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 16) {
+        if (threadIdx.x == 0) status->nonfinite = 0u;
+        status->queue[threadIdx.x] = 0u;
+    }
     // T(h) = h log2 h for every count a group can hold (FP64, 0 for h < 2),
     // and the increments F[c] = R(T(c+1)) - R(T(c)) with R the rounding to the
     // grid 2^-K: sums of increments telescope to R(T(h)) exactly, in any order
@@ -778,11 +865,13 @@ int device_cus() {
     return cached;
 }
 
-// Static LDS of a kernel variant (everything but the histogram words).
+// Static LDS of a kernel variant (everything but the histogram words), with
+// room for the tile index of the persistent grid and the 16-byte alignment
+// of the histogram words.
 static int static_lds_bytes(int nt) {
     int nw = nt / MGS_WAVE;
     return (int)(2 * sizeof(double) * LGTAB + 2 * sizeof(double) * MGS_MAX_BITS * nw + 4 * 4 * nw +
-                 2 * 4 * MGS_MAX_BITS) + 256;
+                 2 * 4 * MGS_MAX_BITS + sizeof(int64_t)) + 256 + 16;
 }
 
 bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p) {
@@ -962,8 +1051,15 @@ int launch_sweep(const SweepParams& p, const Shape& sh, size_t lds,
     const Variant* v = find_variant(sh.nt, sh.ept, G);
     if (!v) return MGS_EINVAL;
     // one workgroup per tile, rounded up to whole XCD rounds (the extra
-    // workgroups find no tile)
-    if (grid <= 0 || grid > p.ntiles) grid = (p.ntiles + MGS_XCDS - 1) / MGS_XCDS * MGS_XCDS;
+    // workgroups find no tile); a persistent grid fills every resident slot
+    // of the device (whole XCD rounds), but never exceeds that first grid
+    const int64_t per_tile = (p.ntiles + MGS_XCDS - 1) / MGS_XCDS * MGS_XCDS;
+    if (p.persist) {
+        const int64_t slots = (int64_t)max_resident_blocks(sh, lds, G) * device_cus();
+        grid = std::min(per_tile, std::max<int64_t>(MGS_XCDS, slots / MGS_XCDS * MGS_XCDS));
+    } else if (grid <= 0 || grid > p.ntiles) {
+        grid = per_tile;
+    }
     if (p.ntiles < 1) return MGS_OK;
     if (grid > 0x7fffffff) grid = 0x7fffffff;
     return v->fn(p, grid, lds, s) == hipSuccess ? MGS_OK : MGS_EDEVICE;
@@ -994,6 +1090,7 @@ int increment_grid_bits(int G) {
 int max_resident_blocks(const Shape& sh, size_t lds, int G) {
     const Variant* v = find_variant(sh.nt, sh.ept, G);
     if (!v) return 1;
+    if (lds > 65536) (void)hipFuncSetAttribute(v->kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int nblk = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, v->kern, sh.nt, lds) != hipSuccess ||
         nblk < 1)
@@ -1125,6 +1222,7 @@ static int sweep_launch_scenes(mgs::SceneDesc* scs, int n, void* d_ws, size_t ws
     p.lgtab = lgtab;
     p.lgtab_max = s0.G;
     p.kgrid = increment_grid_bits(s0.G);
+    p.persist = sh.persist;
     if (p.ntiles == 0) return MGS_OK;
     return launch_sweep(p, sh, lds, 0, s, s0.G);
 }
@@ -1218,21 +1316,27 @@ static const int kCpbs[] = {0, 4, 2, 1};
 static constexpr int kNumCaps = (int)(sizeof(kLdsCaps) / sizeof(kLdsCaps[0]));
 static constexpr int kNumCpbs = (int)(sizeof(kCpbs) / sizeof(kCpbs[0]));
 
-extern "C" int mgs_sweep_shape_count(void) { return mgs::variant_count() * kNumCaps * kNumCpbs; }
+static constexpr int kShapesPerVariant = kNumCaps * kNumCpbs * 2;  // x {tile grid, persistent}
+
+extern "C" int mgs_sweep_shape_count(void) { return mgs::variant_count() * kShapesPerVariant; }
+
+static int candidate_variant(int i) { return i / kShapesPerVariant; }
 
 static mgs::Shape candidate_shape(int i) {
-    mgs::Shape sh = mgs::variant_shape(i / (kNumCaps * kNumCpbs));
-    sh.lds_cap = kLdsCaps[(i / kNumCpbs) % kNumCaps];
-    sh.cpb = kCpbs[i % kNumCpbs];
+    mgs::Shape sh = mgs::variant_shape(candidate_variant(i));
+    const int r = i % kShapesPerVariant;
+    sh.lds_cap = kLdsCaps[(r / (kNumCpbs * 2)) % kNumCaps];
+    sh.cpb = kCpbs[(r / 2) % kNumCpbs];
+    sh.persist = r % 2;
     return sh;
 }
 
 extern "C" int mgs_sweep_set_shape(int32_t G, int32_t nb, int32_t bmax, int32_t nt, int32_t ept,
-                                   int32_t lds_cap, int32_t cpb) {
+                                   int32_t lds_cap, int32_t cpb, int32_t persist) {
     if (G < 1 || G > MGS_MAX_GROUP || nb < 1 || nb > MGS_MAX_BITS || bmax < 1 || bmax > MGS_MAX_BITS ||
-        cpb < 0)
+        cpb < 0 || persist < 0 || persist > 1)
         return MGS_EINVAL;
-    mgs::Shape sh{nt, ept, lds_cap < 0 ? 0 : lds_cap, cpb};
+    mgs::Shape sh{nt, ept, lds_cap < 0 ? 0 : lds_cap, cpb, persist};
     if (nt != 0 && !mgs::shape_valid(sh, G)) return MGS_EINVAL;
     mgs::set_tuned_shape(G, nb, bmax, sh);  // nt == 0 clears (falls back to the default)
     return MGS_OK;
@@ -1255,20 +1359,23 @@ extern "C" int mgs_sweep_autotune(const mgs_sweep_desc* desc, const float* d_att
         return MGS_EDEVICE;
     }
     const int n = mgs_sweep_shape_count();
-    float best_ms = -1.0f;
-    Shape best{0, 0, 0, 0};
     int status = MGS_OK;
+    // every candidate's time (-1: does not apply), kept for the near-tie rule
+    float times[1024];
+    if (n > 1024) return MGS_EINVAL;
+    for (int i = 0; i < n; ++i) times[i] = -1.0f;
     for (int i = 0; i < n && status == MGS_OK; ++i) {
         Shape sh = candidate_shape(i);
         if (h_shapes) {
-            h_shapes[4 * i] = sh.nt;
-            h_shapes[4 * i + 1] = sh.ept;
-            h_shapes[4 * i + 2] = sh.lds_cap;
-            h_shapes[4 * i + 3] = sh.cpb;
+            h_shapes[5 * i] = sh.nt;
+            h_shapes[5 * i + 1] = sh.ept;
+            h_shapes[5 * i + 2] = sh.lds_cap;
+            h_shapes[5 * i + 3] = sh.cpb;
+            h_shapes[5 * i + 4] = sh.persist;
         }
         if (h_ms) h_ms[i] = -1.0f;
         const int64_t capacity = (int64_t)sh.nt * sh.ept;
-        const bool chunked = variant_chunked(i / (kNumCaps * kNumCpbs));
+        const bool chunked = variant_chunked(candidate_variant(i));
         if (chunked != (capacity < sc.G)) continue;
         if (!chunked && capacity >= 4 * (int64_t)std::max(sc.G, 256)) continue;  // mostly idle lanes
         if (!shape_valid(sh, sc.G)) continue;
@@ -1294,21 +1401,37 @@ extern "C" int mgs_sweep_autotune(const mgs_sweep_desc* desc, const float* d_att
         }
         if (status) break;
         if (h_ms) h_ms[i] = tmin;
-        if (best_ms < 0.0f || tmin < best_ms) {
-            best_ms = tmin;
-            best = sh;
-        }
+        times[i] = tmin;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status) return status;
-    if (best.nt == 0) return MGS_EINVAL;
+    // the fastest shape, except that among shapes within 3 % of it the one
+    // with more channels per tile (fewer tiles, so fewer fetches of the
+    // tiles' indices and weights) wins; then the faster one
+    float best_ms = -1.0f;
+    for (int i = 0; i < n; ++i)
+        if (times[i] >= 0.0f && (best_ms < 0.0f || times[i] < best_ms)) best_ms = times[i];
+    if (best_ms < 0.0f) return MGS_EINVAL;
+    auto chans = [&](const Shape& sh) { return sh.cpb > 0 ? std::min(sh.cpb, sc.C) : sc.C; };
+    int bi = -1;
+    for (int i = 0; i < n; ++i) {
+        if (times[i] < 0.0f || times[i] > 1.03f * best_ms) continue;
+        if (bi < 0) {
+            bi = i;
+            continue;
+        }
+        const int ci = chans(candidate_shape(i)), cb = chans(candidate_shape(bi));
+        if (ci > cb || (ci == cb && times[i] < times[bi])) bi = i;
+    }
+    const Shape best = candidate_shape(bi);
     set_tuned_shape(sc.G, sc.nb, sc.bmax, best);
     if (h_best) {
         h_best[0] = best.nt;
         h_best[1] = best.ept;
         h_best[2] = best.lds_cap;
         h_best[3] = best.cpb;
+        h_best[4] = best.persist;
     }
     // leave the tables as the chosen shape computes them
     return sweep_launch(desc, d_attr, d_imp, d_kept, d_err, d_bits, d_gmin, d_gmax, nullptr, d_ws,

@@ -55,7 +55,7 @@ SIGNATURES = {
     "mgs_quant_sweep_multi": (ct.c_int, [P, I32, P, SZ, P]),
     "mgs_sweep_shape_count": (ct.c_int, []),
     "mgs_sweep_autotune": (ct.c_int, [P, P, P, P, P, P, P, P, P, SZ, P, I32, P, P, P]),
-    "mgs_sweep_set_shape": (ct.c_int, [I32, I32, I32, I32, I32, I32, I32]),
+    "mgs_sweep_set_shape": (ct.c_int, [I32, I32, I32, I32, I32, I32, I32, I32]),
     "mgs_quantize": (ct.c_int, [P, I64, I32, P, I64, I32, P, P, P, P, P]),
     "mgs_dequantize": (ct.c_int, [P, I64, I32, I32, P, P, P, P, P]),
     "mgs_vq_assign_ws_bytes": (SZ, [I64, I32, I32]),
@@ -321,7 +321,7 @@ def capture(fn, stream):
 def sweep_autotune(attr, imp, kept, k, G: int, bits, reps: int = 3, ws=None, out=None, stream=None):
     """Time every launch shape of the sweep on these inputs and register the fastest.
 
-    Returns ``(best (nt, ept, lds_cap, cpb), [(nt, ept, lds_cap, cpb, ms), ...])``.
+    Returns ``(best (nt, ept, lds_cap, cpb, persist), [(nt, ept, lds_cap, cpb, persist, ms), ...])``.
     """
     torch = _torch()
     C, N = attr.shape
@@ -339,18 +339,19 @@ def sweep_autotune(attr, imp, kept, k, G: int, bits, reps: int = 3, ws=None, out
                "gmax": torch.empty((T, C, gm), dtype=torch.float32, device=dev)}
     n = lib().mgs_sweep_shape_count()
     ms = np.empty(n, dtype=np.float32)
-    shapes = np.empty((n, 4), dtype=np.int32)
-    best = np.empty(4, dtype=np.int32)
+    shapes = np.empty((n, 5), dtype=np.int32)
+    best = np.empty(5, dtype=np.int32)
     _check(lib().mgs_sweep_autotune(ct.byref(d), _dptr(attr), _dptr(imp), _dptr(kept), _dptr(out["err"]),
                                     _dptr(out["bits"]), _dptr(out["gmin"]), _dptr(out["gmax"]), _dptr(ws),
                                     ws.numel(), _stream(stream), reps, _np_ptr(ms), _np_ptr(shapes),
                                     _np_ptr(best)), "mgs_sweep_autotune")
-    rows = [(int(a), int(b), int(c), int(d), float(m)) for (a, b, c, d), m in zip(shapes, ms) if m >= 0]
+    rows = [tuple(int(v) for v in sh) + (float(m),) for sh, m in zip(shapes, ms) if m >= 0]
     return tuple(int(v) for v in best), rows
 
 
-def sweep_set_shape(G: int, nb: int, bmax: int, nt: int, ept: int, lds_cap: int = 0, cpb: int = 0):
-    _check(lib().mgs_sweep_set_shape(G, nb, bmax, nt, ept, lds_cap, cpb), "mgs_sweep_set_shape")
+def sweep_set_shape(G: int, nb: int, bmax: int, nt: int, ept: int, lds_cap: int = 0, cpb: int = 0,
+                    persist: int = 0):
+    _check(lib().mgs_sweep_set_shape(G, nb, bmax, nt, ept, lds_cap, cpb, persist), "mgs_sweep_set_shape")
 
 
 def quantize(attr, kept, G: int, bw, stream=None):
@@ -450,6 +451,23 @@ def raht(codes, values, depth: int, inverse: bool = False, ws=None, stream=None,
            "mgs_raht_inverse" if inverse else "mgs_raht_forward")
     _finish(ws, check, "mgs_raht", stream)
     return out
+
+
+def raht_sweep(codes, attr, depth: int, G: int, bits, ws=None, stream=None, check: bool = True):
+    """The quantization sweep over RAHT coefficients (the paper quantizes the AC
+    coefficients group-wise and keeps the DC in floating point): RAHT forward of
+    ``attr`` (f32 [C][N], Morton order of ``codes``), then one sweep over the
+    N - 1 AC columns of every channel, in the order the transform makes them,
+    with unit weights (the unweighted squared error).  Returns ``(coef f32
+    [C][N], tables)``; the tables have one reserve ratio keeping all N - 1 ACs."""
+    torch = _torch()
+    C, N = attr.shape
+    coef = raht(codes, attr, depth, stream=stream, check=check)
+    n_ac = N - 1
+    kept = torch.arange(1, N, dtype=torch.int32, device=attr.device)
+    ones = torch.ones(N, dtype=torch.float32, device=attr.device)
+    tab = quant_sweep(coef, ones, kept, [n_ac], G, bits, ws=ws, stream=stream, check=check)
+    return coef, tab
 
 
 # ----------------------------------------------------------------- host side

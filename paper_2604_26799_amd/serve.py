@@ -11,8 +11,9 @@ Batched mode (continuous batching):
   * an admitted job's scene is uploaded on a copy stream, then pruned on the
     compute stream;
   * every device iteration launches ONE multi-scene sweep over all jobs that
-    are ready (mgs_quant_sweep_multi), so jobs that arrive while others run
-    join the next launch;
+    are ready (mgs_quant_sweep_multi); at most `max_inflight` such launches
+    are on the GPU at a time, so jobs that become ready while one runs wait
+    for it and join the next launch together (iteration-level scheduling);
   * each job's tables come back to pinned host memory and its ILP search runs
     on a host thread pool while the GPU keeps sweeping other jobs;
   * the chosen bit-widths go back, the final codes are quantized on the
@@ -134,7 +135,8 @@ class Server:
 
     def __init__(self, store: SceneStore, G: int = 8192, bits=range(2, 17), mode: str = "batched",
                  mem_cap_bytes: int = 32 << 30, host_workers: int = 4, ilp_threads: int = 0,
-                 keep_codes: bool = False, max_batch: int = mgs.MAX_JOBS, warm_up: bool = True):
+                 keep_codes: bool = False, max_batch: int = mgs.MAX_JOBS, warm_up: bool = True,
+                 max_inflight: int = 1):
         import torch
         assert mode in ("batched", "plain")
         self.torch = torch
@@ -146,6 +148,8 @@ class Server:
         self.adm = Admission(mem_cap_bytes if mode == "batched" else 0)  # plain: one job at a time
         self.keep_codes = keep_codes
         self.max_batch = max_batch
+        self.max_inflight = max(1, int(max_inflight))
+        self.inflight: List = []  # events of the sweep launches on the GPU
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.compute = torch.cuda.Stream()   # default priority
         self.copy = torch.cuda.Stream()
@@ -248,6 +252,7 @@ class Server:
             ev.record(self.compute)
         for b in batch:
             b.ev = ev
+        self.inflight.append(ev)
         self.batch_sizes.append(len(batch))
 
     def _plain_sweep(self, b: _Live):
@@ -346,13 +351,16 @@ class Server:
                 progressed = True
             # jobs of a launch whose status word flagged non-finite data are
             # swept again one per launch, so the flag names the job
-            while solo:
+            while solo and len(self.inflight) < self.max_inflight:
                 one = solo.popleft()
                 self._launch_sweep([one])
                 sweeping.append(one)
                 progressed = True
-            # one sweep launch over every ready job (plain: the oldest one)
-            if ready:
+            # one sweep launch over every ready job (plain: the oldest one),
+            # once a launch slot is free: jobs that get ready meanwhile gather
+            # for the next launch
+            self.inflight = [e for e in self.inflight if not e.query()]
+            if ready and len(self.inflight) < self.max_inflight:
                 if self.mode == "batched":
                     batch, ready = ready[:self.max_batch], ready[self.max_batch:]
                 else:

@@ -148,7 +148,8 @@ def test_sweep_adversarial(torch, orc, G):
 
 def test_sweep_every_shape_identical(torch, orc):
     """Launch shapes (threads, elements per thread, LDS capacity, channels per
-    tile, chunked) change nothing beyond the summation order of the loss:
+    tile, chunked, persistent grid) change nothing beyond the summation order
+    of the loss:
     every shape matches the oracle, shapes agree with each other within the
     loss bound (sizes to 1e-12), group bounds exactly, and a repeated launch
     of one shape is bit-identical."""
@@ -159,7 +160,9 @@ def test_sweep_every_shape_identical(torch, orc):
     want = orc.quant_sweep(attr, imp, kept, k, G, bits)
     first = None
     shapes = [(256, 16, 0, 0), (512, 8, 0, 1), (1024, 4, 65536, 3), (512, 16, 98304, 7),
-              (1024, 8, 0, 20), (256, 32, 65536, 2), (512, 16, 65536, 1)]
+              (1024, 8, 0, 20), (256, 32, 65536, 2), (512, 16, 65536, 1),
+              # persistent grids: tiles from the per-XCD counters
+              (512, 16, 98304, 4, 1), (1024, 8, 0, 0, 1), (256, 32, 65536, 2, 1), (1024, 16, 0, 1, 1)]
     try:
         for sh in shapes:
             mgs.sweep_set_shape(G, len(bits), max(bits), *sh)
@@ -177,10 +180,11 @@ def test_sweep_every_shape_identical(torch, orc):
                 np.testing.assert_allclose(got["err"][ok], first["err"][ok], rtol=2 * ERR_REL)
                 np.testing.assert_allclose(got["bits"][ok], first["bits"][ok], rtol=1e-12, atol=1e-9)
         # a group larger than the shape's capacity takes the chunked kernel
-        mgs.sweep_set_shape(16384, len(bits), max(bits), 512, 16, 0, 5)
         want = orc.quant_sweep(attr, imp, kept, k, 16384, bits)
-        got = gpu_sweep(torch, attr, imp, kept, k, 16384, bits, hist=False)
-        assert_tables(got, want, hist=False, G=16384)
+        for persist in (0, 1):
+            mgs.sweep_set_shape(16384, len(bits), max(bits), 512, 16, 0, 5, persist)
+            got = gpu_sweep(torch, attr, imp, kept, k, 16384, bits, hist=False)
+            assert_tables(got, want, hist=False, G=16384)
     finally:
         mgs.sweep_set_shape(G, len(bits), max(bits), 0, 0, 0, 0)
         mgs.sweep_set_shape(16384, len(bits), max(bits), 0, 0, 0, 0)
@@ -445,10 +449,11 @@ def test_vq_workload_sampled(torch, orc):
 
 
 def test_kmeans_steps(torch, orc):
-    """Mini-batch k-means iterations on SH-like vectors: assignments and counts
-    exact, centers within an FP32 ulp of the oracle's per-sample updates (the
-    library's FP64 running mean differs only by rounding order); every
-    iteration starts both sides from the library's state."""
+    """Mini-batch k-means iterations on SH-like vectors: assignments, counts and
+    centers bit-identical to the oracle's batched running mean (each center's
+    rows summed in batch order), centers within FP32 rounding of the
+    per-sample updates, and a repeat of the same step gives the same bits;
+    every iteration starts both sides from the library's state."""
     x, cb = synth.vq_data(20_000, 36, 128, seed=4)
     rng = np.random.default_rng(4)
     counts = np.zeros(128, np.int64)
@@ -459,11 +464,18 @@ def test_kmeans_steps(torch, orc):
     for it in range(3):
         batch = rng.integers(0, x.shape[0], 4096)
         c0, v0 = host(cbd).copy(), host(cd).copy()
+        # the same step twice from the same state: identical bits
+        again_c, again_v = dev(torch, c0), dev(torch, v0)
+        mgs.kmeans_step(xd, again_c, again_v, dev(torch, batch))
         a = mgs.kmeans_step(xd, cbd, cd, dev(torch, batch))
         torch.cuda.synchronize()
+        assert np.array_equal(host(again_c), host(cbd)) and np.array_equal(host(again_v), host(cd)), it
+        bc, bv, ba = orc.kmeans_step_batched(x, c0, v0, batch)
+        assert np.array_equal(host(a), ba), it
+        assert np.array_equal(host(cd), bv), it
+        assert np.array_equal(host(cbd), bc), it
         wc, wv, wa = orc.kmeans_step(x, c0, v0, batch)
         assert np.array_equal(host(a), wa), it
-        assert np.array_equal(host(cd), wv), it
         np.testing.assert_allclose(host(cbd), wc, rtol=2.5e-7, atol=1e-9)
     # an empty batch changes nothing
     c0 = host(cbd).copy()
@@ -520,3 +532,49 @@ def test_raht_rejects_unsorted_codes(torch, orc):
     with pytest.raises(mgs.MgsError) as e:
         mgs.raht(dev(torch, codes), dev(torch, np.ones((1, 3), np.float32)), 2)
     assert e.value.code == mgs.ENONFINITE
+
+
+@pytest.mark.parametrize("n,depth,C,G,bits", [(30000, 10, 3, 4096, [2, 5, 8, 12, 16]),
+                                               (100000, 14, 20, 8192, list(range(2, 17)))])
+def test_raht_then_sweep(torch, orc, n, depth, C, G, bits):
+    """The sweep over RAHT AC coefficients (DC kept in floating point, unit
+    weights) against the oracle's RAHT followed by the oracle's sweep: every
+    table entry and the search's allocation on both tables."""
+    from paper_2604_26799_amd import synth
+    coords = synth.voxels(n, depth, seed=n)
+    codes = orc.morton(coords, depth)
+    order = np.argsort(codes)
+    coords, codes = coords[order], codes[order]
+    attr, _ = synth.scene(n, 20, seed=depth)
+    attr = np.ascontiguousarray(attr[:C])
+    coef, tab = mgs.raht_sweep(dev(torch, codes.view(np.int64)), dev(torch, attr), depth, G, bits)
+    torch.cuda.synchronize()
+    want_coef = orc.raht_forward(coords, attr, depth)
+    assert np.array_equal(host(coef), want_coef)
+    want = orc.quant_sweep(want_coef, np.ones(n, np.float32), np.arange(1, n, dtype=np.int32),
+                           np.array([n - 1]), G, bits)
+    got = {key: host(v) for key, v in tab.items() if v is not None}
+    assert_tables(got, want, hist=False, G=G)
+    budget = (n - 1) * C * 32 // 20
+    a = mgs.search(n - 1, C, [n - 1], G, bits, got["err"], got["bits"], budget)
+    b = mgs.search(n - 1, C, [n - 1], G, bits, want["err"], want["bits"], budget)
+    assert a["best_t"] == b["best_t"] == 0
+    assert np.array_equal(a["best_bits"], b["best_bits"])
+
+
+def test_kmeans_one_center_takes_all(torch, orc):
+    """Every batch row nearest to one center (a run of 20,000 rows summed in
+    batch order) and centers that get nothing: bit-identical to the oracle's
+    batched running mean."""
+    rng = np.random.default_rng(14)
+    x = rng.normal(0, 0.01, (30_000, 36)).astype(np.float32)
+    cb = np.full((16, 36), 100.0, np.float32)
+    cb[5] = 0.0
+    counts = np.arange(16, dtype=np.int64)
+    batch = rng.integers(0, x.shape[0], 20_000)
+    cbd, cd = dev(torch, cb), dev(torch, counts)
+    a = mgs.kmeans_step(dev(torch, x), cbd, cd, dev(torch, batch))
+    torch.cuda.synchronize()
+    bc, bv, ba = orc.kmeans_step_batched(x, cb, counts, batch)
+    assert (ba == 5).all() and np.array_equal(host(a), ba)
+    assert np.array_equal(host(cd), bv) and np.array_equal(host(cbd), bc)

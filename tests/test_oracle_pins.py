@@ -494,6 +494,37 @@ def test_kmeans_step_is_the_running_mean(orc):
     assert np.array_equal(a, d.argmin(1))
 
 
+def test_kmeans_step_batched(orc):
+    """The batched running mean: the hand-worked step above gives the same
+    centers (0 -> (1*0 + 1 + 2)/3 = 1, 10 -> (10 + 9)/2 = 9.5, and 5/3 for a
+    center with nothing absorbed); on random data it agrees with the
+    per-sample updates within FP32 rounding, assignments and counts equal."""
+    x = np.array([[1.0], [2.0], [9.0]], np.float32)
+    cb = np.array([[0.0], [10.0]], np.float32)
+    c, v, a = orc.kmeans_step_batched(x, cb, [1, 1], [0, 1, 2])
+    assert a.tolist() == [0, 0, 1] and v.tolist() == [3, 2]
+    assert c[:, 0].tolist() == [1.0, 9.5]
+    c, v, a = orc.kmeans_step_batched(x, cb, [0, 5], [1, 0, 1])
+    assert c[0, 0] == np.float32(5.0 / 3.0) and c[1, 0] == 10.0 and v.tolist() == [3, 5]
+    rng = np.random.default_rng(9)
+    x = rng.normal(0, 1, (400, 6)).astype(np.float32)
+    cb = x[rng.choice(400, 9, replace=False)].copy()
+    counts = rng.integers(0, 30, 9)
+    batch = rng.integers(0, 400, 200)
+    cs, vs, as_ = orc.kmeans_step(x, cb, counts, batch)
+    cbt, vb, ab = orc.kmeans_step_batched(x, cb, counts, batch)
+    assert np.array_equal(as_, ab) and np.array_equal(vs, vb)
+    np.testing.assert_allclose(cbt, cs, rtol=3e-7, atol=1e-7)
+    # the rows of a center are summed one after another in batch order
+    j = int(ab[0])
+    mine = x[batch[ab == j]].astype(np.float64)
+    seq = np.zeros(6)
+    for r in mine:
+        seq = seq + r
+    want = ((np.float64(counts[j]) * cb[j].astype(np.float64) + seq) / np.float64(counts[j] + mine.shape[0]))
+    assert np.array_equal(cbt[j], want.astype(np.float32))
+
+
 def test_vq_retain_by_hand(orc):
     """130 remaining bits hold two 2-dim FP32 vectors (64 bits each): the two
     most important Gaussians (importance 5 at index 4, 4 at index 2) keep
