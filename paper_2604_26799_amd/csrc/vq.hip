@@ -28,6 +28,12 @@
 //      smallest (distance, index) wins.  Rows with more candidate tiles than
 //      slots go to an exact FP64 full scan.
 // The result equals the FP64 definition bit for bit.
+//
+// Layout.  The prepared codebook is stored chunk by chunk (64 codewords) as
+// 16-byte units, unit-major: unit u of codeword r of a chunk sits at unit
+// index u * 64 + r.  A chunk is one contiguous block (copied straight into
+// LDS), and the 32 lanes that read one unit of 32 codewords read 512
+// contiguous bytes, free of bank conflicts.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -75,14 +81,15 @@ __global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     float nrm = 0.0f;  // FP32 bits of non-negative floats order as unsigned ints
     if (j < a.Kpad) {
-        bf16x8* row = (bf16x8*)(a.cbp + (int64_t)j * KP);
+        // unit u of codeword j: chunk j / 64, unit-major inside the chunk
+        bf16x8* row = (bf16x8*)(a.cbp + (int64_t)(j / VQ_CHUNK) * VQ_CHUNK * KP) + (j % VQ_CHUNK);
         if (j >= a.K) {
 #pragma unroll
             for (int u = 0; u < KP / 8; ++u) {
                 bf16x8 z;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) z[i] = (__bf16)(8 * u + i == a.D ? 1.0e30f : 0.0f);
-                row[u] = z;  // padding codewords score ~1e30 and are skipped
+                row[u * VQ_CHUNK] = z;  // padding codewords score ~1e30 and are skipped
             }
         } else {
             const float* c = a.cb + (int64_t)j * a.D;
@@ -107,7 +114,7 @@ __global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
                     const int k = 8 * u + i;
                     w[i] = (__bf16)(k < a.D ? -2.0f * v[k] : k == a.D ? hi : k == a.D + 1 ? lo : 0.0f);
                 }
-                row[u] = w;
+                row[u * VQ_CHUNK] = w;
             }
             if (bad) atomicOr(&a.status->nonfinite, 1u);
             nrm = (float)sqrt(n2) * (1.0f + 1.0e-6f);
@@ -272,12 +279,15 @@ void vq_main_kernel(VqArgs a) {
         // chunk 0) while this one is processed
         if (q + 1 < 2 * nchunks) prefetch(q + 1 == nchunks ? 0 : c0 + VQ_CHUNK, other);
         // scores of one 32-codeword tile for the wave's row sets; K steps
-        // outer, row sets inner: consecutive MFMAs are independent
+        // outer, row sets inner: consecutive MFMAs are independent.  Lane l
+        // reads unit 2 ks + (l / 32) of codeword tile * 32 + l % 32: 512
+        // contiguous bytes per half-wave
         auto scores = [&](int tile, f32x16 (&acc)[VQ_ROWSETS]) {
             bf16x8 areg[KS];
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
-                areg[ks] = *(const bf16x8*)(cb_l + (tile * 32 + (lane & 31)) * KP + 16 * ks + 8 * half);
+                areg[ks] = *(const bf16x8*)((const char*)cb_l +
+                                            (size_t)(((2 * ks + half) * VQ_CHUNK) + tile * 32 + (lane & 31)) * 16);
 #pragma unroll
             for (int rs = 0; rs < VQ_ROWSETS; ++rs) acc[rs] = f32x16{};
 #pragma unroll
