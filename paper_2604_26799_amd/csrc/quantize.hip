@@ -5,9 +5,9 @@
 //
 // Both kernels are HBM-bound: one workgroup per (channel, group) reads the
 // group's values once for the minimum / maximum and keeps them in registers
-// for the codes (groups beyond 8192 elements (1024 threads) or 2048 (256
-// threads) read them again, from L2); the dequantizer reads 2-byte codes and
-// writes FP32 values.  The
+// for the codes (up to 16 values per thread: groups beyond 16384 elements
+// (1024 threads) or 2048 (256 threads) read them again, from L2); the
+// dequantizer reads 2-byte codes and writes FP32 values.  The
 // quantizer expression is the literal FP32 definition, so codes equal those
 // of the sweep bit for bit.
 #include <algorithm>
@@ -17,7 +17,7 @@
 namespace mgs {
 namespace {
 
-constexpr int QU = 8;  // elements per thread and batch: independent loads in flight
+constexpr int QU = 8;  // dequantizer: elements per thread and batch (independent loads in flight)
 
 __device__ __forceinline__ int clamp_bits(uint8_t b) { return b < 1 ? 1 : (b > 16 ? 16 : b); }
 
@@ -26,7 +26,7 @@ __device__ __forceinline__ int clamp_bits(uint8_t b) { return b < 1 ? 1 : (b > 1
 // first issues its QU index loads, then its QU value loads, so that each
 // thread has QU gathers in flight instead of one.  Groups of up to QT * QU
 // elements stay in registers between the minimum / maximum and the codes.
-template <int QT>
+template <int QT, int QU>
 __global__ __launch_bounds__(QT) void quantize_kernel(const float* __restrict__ attr, int64_t ld,
                                                       int C, const int32_t* __restrict__ kept,
                                                       int64_t k, int G, int64_t ng,
@@ -179,13 +179,18 @@ extern "C" int mgs_quantize(const float* d_attr, int64_t ld, int32_t C, const in
     if (!d_attr || !d_kept || !d_bw || !d_codes || !d_gmin || !d_gmax) return MGS_EINVAL;
     const int64_t ng = (k + G - 1) / G;
     const int64_t blocks = std::min<int64_t>((int64_t)C * ng, 1 << 20);
-    // large groups: 1024 threads per group; small ones: 256
-    if (G >= 4096)
-        hipLaunchKernelGGL(mgs::quantize_kernel<1024>, dim3((unsigned)blocks), dim3(1024), 0,
+    // large groups: 1024 threads per group, 8 or 16 values per thread (a group
+    // of up to 16384 is gathered once); small ones: 256 threads
+    if (G > 8192)
+        hipLaunchKernelGGL((mgs::quantize_kernel<1024, 16>), dim3((unsigned)blocks), dim3(1024), 0,
+                           (hipStream_t)stream, d_attr, ld, C, d_kept, k, G, ng, d_bw, d_codes, d_gmin,
+                           d_gmax);
+    else if (G >= 4096)
+        hipLaunchKernelGGL((mgs::quantize_kernel<1024, 8>), dim3((unsigned)blocks), dim3(1024), 0,
                            (hipStream_t)stream, d_attr, ld, C, d_kept, k, G, ng, d_bw, d_codes, d_gmin,
                            d_gmax);
     else
-        hipLaunchKernelGGL(mgs::quantize_kernel<256>, dim3((unsigned)blocks), dim3(256), 0,
+        hipLaunchKernelGGL((mgs::quantize_kernel<256, 8>), dim3((unsigned)blocks), dim3(256), 0,
                            (hipStream_t)stream, d_attr, ld, C, d_kept, k, G, ng, d_bw, d_codes, d_gmin,
                            d_gmax);
     return mgs_last_launch();
