@@ -13,13 +13,16 @@ constexpr int MGS_XCDS = 8;           // XCDs that workgroups are dispatched ove
 
 // One histogram window of one bit-width inside a batch of LDS words.
 struct HistEntry {
-    int16_t bi;       // index into the bit-width list
-    uint8_t packed;   // two 16-bit bins per 32-bit word
-    uint8_t first;    // first window of this b: it also accumulates the loss
-    uint8_t split;    // the b's bins span more than one window
-    uint8_t rtn;      // entropy from the atomics' old counts (no scan of the bins)
-    uint8_t rlog;     // log2 of the copies per bin (lane-interleaved replicas)
-    uint8_t pad;
+    // Every field is a 4-byte word, so that the kernel reads an entry with
+    // scalar loads (sub-word fields at unaligned offsets become vector loads
+    // whose latency each wavefront waits out once per entry).
+    int32_t bi;       // index into the bit-width list
+    int32_t b;        // the bit-width (every scene of a launch has the same list)
+    int32_t packed;   // two 16-bit bins per 32-bit word
+    int32_t first;    // first window of this b: it also accumulates the loss
+    int32_t split;    // the b's bins span more than one window
+    int32_t rtn;      // entropy from the atomics' old counts (no scan of the bins)
+    int32_t rlog;     // log2 of the copies per bin (lane-interleaved replicas)
     int32_t lo;       // first word of the window within the b's words
     int32_t nwords;   // words in the window
     int32_t lds_off;  // word offset of the window inside the batch

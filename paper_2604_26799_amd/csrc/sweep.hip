@@ -581,7 +581,7 @@ void sweep_kernel(SweepParams p) {
                         const int bi = en.bi;
                         const float S = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmS[bi])));
                         const float Z = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(prmZ[bi])));
-                        const float P = ldexpf(1.0f, sc->bl[bi]);
+                        const float P = ldexpf(1.0f, en.b);
                         const float Ss = ldexpf(S, -E);
                         const int base = en.lds_off - en.lo;
                         const int rl = en.rlog;
@@ -908,7 +908,8 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
             for (int lo = 0; lo < it.words; lo += cap_words) {
                 if (nbat == MGS_MAX_ENTRIES || ne == MGS_MAX_ENTRIES) return false;
                 HistEntry e{};
-                e.bi = (int16_t)it.bi;
+                e.bi = it.bi;
+                e.b = bl[it.bi];
                 e.packed = it.packed;
                 e.first = lo == 0;
                 e.split = 1;
@@ -935,9 +936,10 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         }
         if (ne == MGS_MAX_ENTRIES) return false;
         HistEntry e{};
-        e.bi = (int16_t)it.bi;
+        e.bi = it.bi;
+        e.b = bl[it.bi];
         e.packed = it.packed;
-        e.rlog = (uint8_t)it.rlog;
+        e.rlog = it.rlog;
         e.first = 1;
         e.split = 0;
         // more bins than a sixteenth of the elements: the entropy comes from the
