@@ -113,6 +113,11 @@ __device__ __forceinline__ uint32_t big_count_mask(bool packed) {
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
+// A pointer into the constant address space (global memory the kernel only
+// reads and nothing writes while it runs).
+template <typename T>
+using constant_ptr = const __attribute__((address_space(4))) T*;
+
 // LDS byte address of a shared-memory word (LDS addresses are 32-bit).
 __device__ __forceinline__ uint32_t lds_addr(const uint32_t* p) {
     return (uint32_t)(uintptr_t)(const lds_u32*)p;
@@ -421,13 +426,16 @@ void sweep_kernel(SweepParams p) {
         // [c0, c1)
         int sid = 0;
         while (sid + 1 < p.nscenes && p.tcum[sid + 1] <= it) ++sid;
-        const SceneDesc* sc = &p.scenes[sid];
+        // The descriptors and tile orders were written by the init kernel and
+        // stay fixed during this one: read through the constant address
+        // space, so that their uniform fields come in through scalar loads.
+        const constant_ptr<SceneDesc> sc = (constant_ptr<SceneDesc>)(p.scenes + sid);
         int t, c0, g;
         {
             const int64_t lt = it - p.tcum[sid];
             const int64_t gpc = sc->gpc;
             const int cc = (int)(lt / gpc);
-            const int r = sc->order[(int)(lt - (int64_t)cc * gpc)];
+            const int r = ((constant_ptr<int32_t>)sc->order)[(int)(lt - (int64_t)cc * gpc)];
             c0 = cc * p.cpb;
             t = 0;
             while (t + 1 < sc->T && sc->gcum[t + 1] <= r) ++t;
