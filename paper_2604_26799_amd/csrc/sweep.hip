@@ -448,27 +448,36 @@ void sweep_kernel(SweepParams p) {
         const int32_t* J = sc->kept + sc->koff[t] + j0;
         const int nb = sc->nb;
 
-        // ---- per-element state, gathered per channel into registers (a
-        // group beyond NT * EPT elements -- the chunked kernel -- is gathered
-        // per chunk, again for every histogram batch).  The indices and weights
-        // of a tile's later channels come from L1/L2.
+        // ---- per-element state in registers.  The kept indices and the
+        // weights are the same for every channel of the tile: they are
+        // gathered once per tile and held, so that a channel costs one
+        // round trip (its values).  A group beyond NT * EPT elements (the
+        // chunked kernel) is gathered per channel and chunk, again for every
+        // histogram batch, its indices and weights from L1/L2.
         constexpr int CAP = NT * EPT;
         const int nchunk = CHUNKED ? (n + CAP - 1) / CAP : 1;
         float u[EPT], xv[EPT], wv[EPT];
+        int32_t ids[CHUNKED ? 1 : EPT];
 
         const float* imp = sc->imp;
+        if constexpr (!CHUNKED) {
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) ids[i] = i * NT + tid < n ? J[i * NT + tid] : 0;
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) wv[i] = i * NT + tid < n ? imp[ids[i]] : 0.0f;
+        }
         for (int c = c0; c < c1; ++c) {
-            // Opaque copies of the index and weight pointers: otherwise their
-            // loads are hoisted out of the channel loop and held in registers
-            // across all channels, which halves the occupancy.
-            const int32_t* Jc = J;
-            const float* impc = imp;
-            asm volatile("" : "+v"(Jc), "+v"(impc));
             const float* row = sc->attr + (int64_t)c * sc->ld;
             const int64_t slot = ((int64_t)t * sc->C + c) * sc->gmaxn + g;
             float mn = INFINITY, mx = -INFINITY, wm = 0.0f;  // wm: largest |weight|
             uint32_t bad = 0;
             auto gather = [&](int ch) {
+                // Opaque copies of the index and weight pointers: otherwise
+                // their loads are hoisted out of the channel loop and held in
+                // registers across all channels.
+                const int32_t* Jc = J;
+                const float* impc = imp;
+                asm volatile("" : "+v"(Jc), "+v"(impc));
 #pragma unroll
                 for (int i = 0; i < EPT; ++i) {
                     int j = ch * CAP + i * NT + tid;
@@ -489,7 +498,19 @@ void sweep_kernel(SweepParams p) {
             if constexpr (CHUNKED) {
                 for (int ch = nchunk - 1; ch >= 0; --ch) gather(ch);  // ends holding chunk 0
             } else {
-                gather(0);
+#pragma unroll
+                for (int i = 0; i < EPT; ++i) {
+                    float x = 0.0f;
+                    if (i * NT + tid < n) {
+                        x = row[ids[i]];
+                        const float w = wv[i];
+                        bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
+                        mn = fminf(mn, x);
+                        mx = fmaxf(mx, x);
+                        wm = fmaxf(wm, fabsf(w));
+                    }
+                    xv[i] = x;
+                }
             }
             mn = wave_min_dpp(mn);
             mx = wave_max_dpp(mx);
