@@ -70,6 +70,7 @@ struct SweepParams {
     int32_t persist;          // persistent grid: tiles from the per-XCD counters of status->queue
     int32_t batch_begin[MGS_MAX_ENTRIES + 1];
     int32_t batch_words[MGS_MAX_ENTRIES];
+    int32_t batch_scan_end[MGS_MAX_ENTRIES];  // a batch's scanned entries come first: [begin, scan_end)
     HistEntry entries[MGS_MAX_ENTRIES];
 };
 

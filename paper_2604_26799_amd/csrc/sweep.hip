@@ -68,10 +68,15 @@
 namespace mgs {
 
 // h * log2(h) of a bin count (scanned histograms): small counts from the
-// LDS copy, larger ones from the workspace table.
+// LDS copy, larger ones from the workspace table.  The two tables are read
+// through pointers typed with their address spaces: a choice between two
+// generic pointers becomes one flat load, which waits out the latency of
+// global memory on every call.
 __device__ __forceinline__ double hlog2h(uint32_t h, const double* lg, const double* lgt) {
-    double v = lg[h < (uint32_t)LGTAB ? h : 0u];
-    if (h >= (uint32_t)LGTAB) v = lgt[h];
+    typedef const __attribute__((address_space(3))) double lds_f64;
+    typedef const __attribute__((address_space(1))) double glb_f64;
+    double v = ((lds_f64*)lg)[h < (uint32_t)LGTAB ? h : 0u];
+    if (h >= (uint32_t)LGTAB) v = ((glb_f64*)lgt)[h];
     return v;
 }
 
@@ -117,6 +122,9 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 // reads and nothing writes while it runs).
 template <typename T>
 using constant_ptr = const __attribute__((address_space(4))) T*;
+// A pointer into global memory.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
 
 // LDS byte address of a shared-memory word (LDS addresses are 32-bit).
 __device__ __forceinline__ uint32_t lds_addr(const uint32_t* p) {
@@ -475,16 +483,18 @@ void sweep_kernel(SweepParams p) {
                 // Opaque copies of the index and weight pointers: otherwise
                 // their loads are hoisted out of the channel loop and held in
                 // registers across all channels.
-                const int32_t* Jc = J;
-                const float* impc = imp;
+                // (typed global: an opaque generic pointer would make flat loads)
+                global_ptr<const int32_t> Jc = (global_ptr<const int32_t>)J;
+                global_ptr<const float> impc = (global_ptr<const float>)imp;
                 asm volatile("" : "+v"(Jc), "+v"(impc));
+                const global_ptr<const float> rowg = (global_ptr<const float>)row;
 #pragma unroll
                 for (int i = 0; i < EPT; ++i) {
                     int j = ch * CAP + i * NT + tid;
                     float x = 0.0f, w = 0.0f;
                     if (j < n) {
                         int32_t id = Jc[j];
-                        x = row[id];
+                        x = rowg[id];
                         w = impc[id];
                         bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
                         mn = fminf(mn, x);
@@ -565,6 +575,8 @@ void sweep_kernel(SweepParams p) {
                 prmS[tid] = S;
                 prmZ[tid] = Z;
             }
+            // a range that underflows at some b (S_b = 0; S only shrinks with b)
+            const bool anyzero = R / ldexpf(1.0f, sc->bmax) == 0.0f;
             for (int i = tid; i < MGS_MAX_BITS * NW; i += NT) {
                 (&bitpart[0][0])[i] = 0.0;
                 (&errpart[0][0])[i] = 0.0;
@@ -676,14 +688,57 @@ void sweep_kernel(SweepParams p) {
                     }
                 }
                 const bool any_ovf = __syncthreads_or((int)ovf) != 0;
-                // ---- entropy terms of the scanned histograms, the corrections
-                // of incremental ones whose bins outgrew the LDS table (a bin of
+                const bool dbg = sc->hist != nullptr;
+                // ---- entropy terms of the scanned histograms (the batch's
+                // first entries): one lane per bin, which adds up the bin's
+                // 2^rlog copies from its adjacent words (16-byte reads); the
+                // wavefronts take the bins in 64-bin slices, the first slice
+                // of each entry on a wavefront that rotates with the entry, and
+                // only wavefronts that held a slice sum their lanes.
+                if (!dbg) {
+                    for (int e = e0; e < p.batch_scan_end[bt]; ++e) {
+                        const HistEntry en = p.entries[e];
+                        const int rl = en.rlog, R = 1 << rl;
+                        const int nq = en.nwords >> rl;  // bins (packed: words of two bins)
+                        const int first_w = (e * 5) % NW;
+                        const int slice = wave >= first_w ? wave - first_w : wave + NW - first_w;
+                        if (slice * MGS_WAVE >= nq) continue;
+                        double s = 0.0;
+                        for (int q = slice * MGS_WAVE + lane; q < nq; q += NT) {
+                            const uint32_t* src = hist + en.lds_off + (q << rl);
+                            uint32_t h = 0;
+                            if (R >= 4) {
+                                for (int k = 0; k < R; k += 4) {
+                                    const uint4 v = *reinterpret_cast<const uint4*>(src + k);
+                                    h += (v.x + v.y) + (v.z + v.w);
+                                }
+                            } else if (R == 2) {
+                                const uint2 v = *reinterpret_cast<const uint2*>(src);
+                                h = v.x + v.y;
+                            } else {
+                                h = src[0];
+                            }
+                            if (en.packed)
+                                s += hlog2h(h & 0xFFFFu, lg, lgt) + hlog2h(h >> 16, lg, lgt);
+                            else
+                                s += hlog2h(h, lg, lgt);
+                        }
+                        const double tot = wave_total_f64(s);
+                        if (lane == 0) bitpart[en.bi][wave] += tot;
+                    }
+                }
+                // ---- the rest: incremental entries whose range underflows at
+                // this b (every count in bin 0: scanned), the corrections of
+                // incremental ones whose bins outgrew the LDS table (a bin of
                 // h > LGTAB got floor(h / LGTAB) full cycles of the increments plus
                 // the first h mod LGTAB of them, and needs R(T(h)) on the same
-                // grid), and the optional debug copy of the bins
-                for (int e = e0; e < e1; ++e) {
+                // grid), and, with the optional debug copy of the bins, every
+                // entry (scanned ones included)
+                const int e_beg = dbg ? e0 : p.batch_scan_end[bt];
+                const int e_end = (any_ovf || anyzero || dbg) ? e1 : p.batch_scan_end[bt];
+                for (int e = e_beg; e < e_end; ++e) {
                     const HistEntry en = p.entries[e];
-                    const bool scan = !en.rtn || prmS[en.bi] == 0.0f;
+                    const bool scan = !en.rtn || (anyzero && prmS[en.bi] == 0.0f);
                     const bool fix = !scan && any_ovf;
                     uint32_t* hout = sc->hist ? sc->hist + slot * sc->hist_bins + sc->hoff[en.bi] : nullptr;
                     if (!scan && !fix && !hout) continue;
@@ -956,7 +1011,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         }
         int k = 0;
         for (; k < nbat; ++k)
-            if (used[k] + it.words <= cap_words) break;
+            if (used[k] + ((it.words + 3) & ~3) <= cap_words) break;
         if (k == nbat) {
             if (nbat == MGS_MAX_ENTRIES) return false;
             bcount[nbat] = 0;
@@ -978,7 +1033,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         e.lo = 0;
         e.nwords = it.words;
         e.lds_off = used[k];
-        used[k] += it.words;
+        used[k] += (it.words + 3) & ~3;  // every entry starts 16-byte aligned
         bent[k][bcount[k]++] = e;
         ++ne;
     }
@@ -990,7 +1045,13 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         p->batch_begin[k] = e;
         p->batch_words[k] = used[k];
         p->max_batch_words = std::max(p->max_batch_words, used[k]);
-        for (int x = 0; x < bcount[k]; ++x) p->entries[e++] = bent[k][x];
+        // scanned entries first (their order inside a batch changes nothing:
+        // each b has at most one window per batch)
+        for (int x = 0; x < bcount[k]; ++x)
+            if (!bent[k][x].rtn) p->entries[e++] = bent[k][x];
+        p->batch_scan_end[k] = e;
+        for (int x = 0; x < bcount[k]; ++x)
+            if (bent[k][x].rtn) p->entries[e++] = bent[k][x];
     }
     p->batch_begin[nbat] = e;
     return true;
