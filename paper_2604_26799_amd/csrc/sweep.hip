@@ -958,6 +958,18 @@ static int static_lds_bytes(int nt) {
                  2 * 4 * MGS_MAX_BITS + sizeof(int64_t)) + 256 + 16;
 }
 
+#ifndef MGS_RTN_FACTOR
+#define MGS_RTN_FACTOR 0.0625
+#endif
+// Entropy from the atomics' old counts (incremental) instead of a scan of the
+// bins, for bit-widths with more bins than a sixteenth of the group's
+// elements.  The increments add work to every pass, where other wavefronts
+// hide their latency; a scan runs between barriers, with every wavefront of
+// the workgroup waiting on its loads at once (measured crossover).
+static bool incremental_entropy(int b, int G) {
+    return (double)((int64_t)1 << b) > MGS_RTN_FACTOR * (double)G;
+}
+
 bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p) {
     // Greedy: largest histograms first, each into the first batch with room;
     // a b larger than a whole batch is split into windows of cap_words.
@@ -970,7 +982,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
     for (int i = 0; i < nb; ++i) {
         int full = 1 << bl[i];
         bool packed = full > cap_words;
-        bool rtn = (int64_t)16 << bl[i] > G;
+        bool rtn = incremental_entropy(bl[i], G);
         int rlog = 0;
         if (!packed && !rtn)
             while (rlog < REPL_MAX_LOG && (full << (rlog + 1)) <= std::min(REPL_WORDS, cap_words)) ++rlog;
@@ -997,7 +1009,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
                 e.packed = it.packed;
                 e.first = lo == 0;
                 e.split = 1;
-                e.rtn = (int64_t)16 << bl[it.bi] > G;
+                e.rtn = incremental_entropy(bl[it.bi], G);
                 e.lo = lo;
                 e.nwords = std::min(cap_words, it.words - lo);
                 e.lds_off = 0;
@@ -1026,10 +1038,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         e.rlog = it.rlog;
         e.first = 1;
         e.split = 0;
-        // more bins than a sixteenth of the elements: the entropy comes from the
-        // atomics' old counts, which is cheaper than scanning the bins (a scan
-        // costs a fixed latency-bound pass per bit-width; measured crossover)
-        e.rtn = (int64_t)16 << bl[it.bi] > G;
+        e.rtn = incremental_entropy(bl[it.bi], G);
         e.lo = 0;
         e.nwords = it.words;
         e.lds_off = used[k];
