@@ -970,6 +970,17 @@ static bool incremental_entropy(int b, int G) {
     return (double)((int64_t)1 << b) > MGS_RTN_FACTOR * (double)G;
 }
 
+// Two 16-bit bins per LDS word: for a bit-width whose bins do not fit one
+// batch unpacked, and for incremental ones with at least as many bins as the
+// group has elements (counts mostly 0-2; 16 bits hold any group, G <= 65535).
+// Packing costs about five VALU operations per evaluation but halves the
+// words to clear and lets the plan use fewer or smaller batches (measured:
+// 18.4 -> 17.9 ms at G = 16384, b = 1..16).
+static bool packed_bins(int b, int G, int cap_words) {
+    const int64_t full = (int64_t)1 << b;
+    return full > cap_words || (incremental_entropy(b, G) && full >= G);
+}
+
 bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p) {
     // Greedy: largest histograms first, each into the first batch with room;
     // a b larger than a whole batch is split into windows of cap_words.
@@ -981,8 +992,8 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
     Item items[MGS_MAX_BITS];
     for (int i = 0; i < nb; ++i) {
         int full = 1 << bl[i];
-        bool packed = full > cap_words;
         bool rtn = incremental_entropy(bl[i], G);
+        bool packed = packed_bins(bl[i], G, cap_words);
         int rlog = 0;
         if (!packed && !rtn)
             while (rlog < REPL_MAX_LOG && (full << (rlog + 1)) <= std::min(REPL_WORDS, cap_words)) ++rlog;
