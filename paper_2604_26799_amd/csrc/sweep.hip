@@ -366,6 +366,7 @@ void sweep_kernel(SweepParams p) {
     __shared__ float red_mn[NW], red_mx[NW], red_w[NW];
     __shared__ uint32_t red_bad[NW];
     __shared__ float prmS[MGS_MAX_BITS], prmZ[MGS_MAX_BITS];
+    __shared__ uint32_t ovf_flag[MGS_MAX_ENTRIES];  // per batch: some bin passed the LDS increment table
 
     const int tid = threadIdx.x;
     const int lane = tid & (MGS_WAVE - 1);
@@ -595,6 +596,7 @@ void sweep_kernel(SweepParams p) {
                 }
             };
             quotients();
+            for (int i = tid; i < p.nbatches; i += NT) ovf_flag[i] = 0u;
             __syncthreads();
 
             // ---- histogram batches
@@ -687,7 +689,11 @@ void sweep_kernel(SweepParams p) {
                         }
                     }
                 }
-                const bool any_ovf = __syncthreads_or((int)ovf) != 0;
+                // one barrier: the wavefronts that saw a large count flag the
+                // batch before it, everyone reads the flag after it
+                if (__builtin_amdgcn_ballot_w64(ovf != 0u) != 0 && lane == 0) atomicOr(&ovf_flag[bt], 1u);
+                __syncthreads();
+                const bool any_ovf = ovf_flag[bt] != 0u;
                 const bool dbg = sc->hist != nullptr;
                 // ---- entropy terms of the scanned histograms (the batch's
                 // first entries): one lane per bin, which adds up the bin's
@@ -955,7 +961,7 @@ int device_cus() {
 static int static_lds_bytes(int nt) {
     int nw = nt / MGS_WAVE;
     return (int)(2 * sizeof(double) * LGTAB + 2 * sizeof(double) * MGS_MAX_BITS * nw + 4 * 4 * nw +
-                 2 * 4 * MGS_MAX_BITS + sizeof(int64_t)) + 256 + 16;
+                 2 * 4 * MGS_MAX_BITS + 4 * MGS_MAX_ENTRIES + sizeof(int64_t)) + 256 + 16;
 }
 
 #ifndef MGS_RTN_FACTOR
