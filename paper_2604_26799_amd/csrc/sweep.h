@@ -7,7 +7,7 @@ namespace mgs {
 
 constexpr int LGTAB = 256;            // h * log2(h) table entries kept in LDS
 constexpr int MGS_MAX_ENTRIES = 40;   // histogram windows per plan
-constexpr int REPL_WORDS = 1024;      // words a replicated low-b histogram may take
+constexpr int REPL_WORDS = 1024;      // words a replicated low-b histogram may take (G / 8 if more)
 constexpr int REPL_MAX_LOG = 5;       // at most 32 copies per bin
 constexpr int MGS_XCDS = 8;           // XCDs that workgroups are dispatched over, round-robin
 

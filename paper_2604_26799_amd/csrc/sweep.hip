@@ -991,10 +991,16 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
     // Greedy: largest histograms first, each into the first batch with room;
     // a b larger than a whole batch is split into windows of cap_words.
     // Scanned histograms with few bins get lane-interleaved copies (up to
-    // REPL_WORDS words) so that lanes landing in one bin do not serialise on
+    // repl_words words) so that lanes landing in one bin do not serialise on
     // one LDS address.  Fixed-size arrays only: planning allocates nothing.
     struct Item { int bi; int words; bool packed; int rlog; };
     if (nb < 1 || nb > MGS_MAX_BITS) return false;
+    // whole 16-byte units only: every window and entry starts on a unit
+    // boundary (the scans read the copies of a bin as 16-byte units)
+    cap_words &= ~3;
+    // words the copies of one scanned histogram may take: more for larger
+    // groups, whose lanes crowd the same bins more (measured at G = 16384)
+    const int repl_words = std::max(REPL_WORDS, G / 8);
     Item items[MGS_MAX_BITS];
     for (int i = 0; i < nb; ++i) {
         int full = 1 << bl[i];
@@ -1002,7 +1008,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
         bool packed = packed_bins(bl[i], G, cap_words);
         int rlog = 0;
         if (!packed && !rtn)
-            while (rlog < REPL_MAX_LOG && (full << (rlog + 1)) <= std::min(REPL_WORDS, cap_words)) ++rlog;
+            while (rlog < REPL_MAX_LOG && (full << (rlog + 1)) <= std::min(repl_words, cap_words)) ++rlog;
         // insertion keeps equal sizes in list order (a stable sort, largest first)
         Item it{i, packed ? full / 2 : full << rlog, packed, rlog};
         int pos = i;
@@ -1032,7 +1038,7 @@ bool build_plan(const uint8_t* bl, int nb, int cap_words, int G, SweepParams* p)
                 e.lds_off = 0;
                 bent[nbat][0] = e;
                 bcount[nbat] = 1;
-                used[nbat] = e.nwords;
+                used[nbat] = (e.nwords + 3) & ~3;
                 ++nbat;
                 ++ne;
             }
