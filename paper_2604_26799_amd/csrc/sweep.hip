@@ -475,7 +475,16 @@ void sweep_kernel(SweepParams p) {
 #pragma unroll
             for (int i = 0; i < EPT; ++i) wv[i] = i * NT + tid < n ? imp[ids[i]] : 0.0f;
         }
+        // the first batch's bins are cleared before the barrier of the
+        // channel's min/max (the later batches clear their own)
+        auto clear_batch = [&](int bt) {
+            const int words = p.batch_words[bt];
+            uint4* h4 = reinterpret_cast<uint4*>(hist);
+            for (int w = tid; w < (words >> 2); w += NT) h4[w] = make_uint4(0u, 0u, 0u, 0u);
+            for (int w = (words & ~3) + tid; w < words; w += NT) hist[w] = 0u;
+        };
         for (int c = c0; c < c1; ++c) {
+            clear_batch(0);
             const float* row = sc->attr + (int64_t)c * sc->ld;
             const int64_t slot = ((int64_t)t * sc->C + c) * sc->gmaxn + g;
             float mn = INFINITY, mx = -INFINITY, wm = 0.0f;  // wm: largest |weight|
@@ -602,13 +611,10 @@ void sweep_kernel(SweepParams p) {
             // ---- histogram batches
             for (int bt = 0; bt < p.nbatches; ++bt) {
                 const int e0 = p.batch_begin[bt], e1 = p.batch_begin[bt + 1];
-                const int words = p.batch_words[bt];
-                {  // clear the batch's bins, 16 bytes per store
-                    uint4* h4 = reinterpret_cast<uint4*>(hist);
-                    for (int w = tid; w < (words >> 2); w += NT) h4[w] = make_uint4(0u, 0u, 0u, 0u);
-                    for (int w = (words & ~3) + tid; w < words; w += NT) hist[w] = 0u;
+                if (bt > 0) {
+                    clear_batch(bt);
+                    __syncthreads();
                 }
-                __syncthreads();
                 uint32_t ovf = 0;  // some bin grew past the LDS increment table
                 for (int ch = 0; ch < nchunk; ++ch) {
                     if constexpr (CHUNKED) {
