@@ -403,6 +403,24 @@ int mgs_search(const mgs_sweep_desc* desc, const double* h_err, const double* h_
                int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
                int32_t* h_status);
 
+/* mgs_search_streamed: mgs_search while the tables are still arriving on the
+ * host (the same search and results, paper: Algorithm 1), for callers that
+ * copy the tables ratio by ratio so that the host solver starts on the first
+ * ratio instead of waiting for the whole copy.  h_events[t] (a hipEvent_t,
+ * T of them, none NULL) must be recorded after the copies of ratio t's
+ * slices of h_err and h_bits (slot range [t*C*Gmax, (t+1)*C*Gmax) of each);
+ * the search reads ratio t only once it has completed.  It first waits for
+ * the ratios in increasing k_t until one passes the doubled-8-bit test, then
+ * polls the others and bounds each as it lands, so copying the smallest
+ * ratio first and then the rest by decreasing k_t (the costlier bounds
+ * first) starts it soonest.  The events stay owned by the caller.  Returns
+ * MGS_EDEVICE when a wait or poll fails, otherwise as mgs_search (MGS_EINVAL
+ * also for a NULL event). */
+int mgs_search_streamed(const mgs_sweep_desc* desc, const double* h_err, const double* h_bits,
+                        int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t flags,
+                        int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
+                        int32_t* h_status, void* const* h_events);
+
 /* ======================================================================
  * mgs_ilp_hierarchical: the paper's two-step solver (section "Solve the
  * MINLP", paragraph "Hierarchical Solver") for one ILP instance whose

@@ -61,3 +61,33 @@ extern "C" int mgs_graph_destroy(void* graph) {
     if (!graph) return MGS_EINVAL;
     return hipGraphExecDestroy((hipGraphExec_t)graph) == hipSuccess ? MGS_OK : MGS_EDEVICE;
 }
+
+// The host search with a wait per ratio (ilp.cpp); here the waits are the
+// caller's events, one per ratio, recorded after that ratio's table copies.
+namespace mgs {
+int search_tables(const mgs_sweep_desc* d, const double* h_err, const double* h_bits, int64_t budget_bits,
+                  int32_t size_mode, int32_t threads, int32_t flags, int32_t* h_best_t, uint8_t* h_best_bits,
+                  double* h_obj, int64_t* h_used, int32_t* h_status, int (*wait)(void*, int, int), void* wait_ctx);
+}
+
+static int wait_ratio_event(void* ctx, int t, int block) {
+    hipEvent_t e = (hipEvent_t)((void* const*)ctx)[t];
+    if (block) return hipEventSynchronize(e) == hipSuccess ? MGS_OK : MGS_EDEVICE;
+    const hipError_t q = hipEventQuery(e);
+    if (q == hipErrorNotReady) {
+        (void)hipGetLastError();  // not an error: keep it out of the thread's last-error state
+        return 1;
+    }
+    return q == hipSuccess ? MGS_OK : MGS_EDEVICE;
+}
+
+extern "C" int mgs_search_streamed(const mgs_sweep_desc* d, const double* h_err, const double* h_bits,
+                                   int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t flags,
+                                   int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
+                                   int32_t* h_status, void* const* h_events) {
+    if (!d || !h_events || d->T < 1 || d->T > MGS_MAX_RATIOS) return MGS_EINVAL;
+    for (int t = 0; t < d->T; ++t)
+        if (!h_events[t]) return MGS_EINVAL;
+    return mgs::search_tables(d, h_err, h_bits, budget_bits, size_mode, threads, flags, h_best_t, h_best_bits,
+                              h_obj, h_used, h_status, wait_ratio_event, (void*)h_events);
+}

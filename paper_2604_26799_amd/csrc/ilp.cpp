@@ -25,6 +25,7 @@
 // Among optimal solutions the smaller total size wins, then the smaller
 // option index in class order.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <climits>
 #include <cstdint>
@@ -33,6 +34,7 @@
 #include <limits>
 #include <memory>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include <omp.h>
@@ -834,10 +836,15 @@ static bool ratio_instance(const mgs_sweep_desc* d, const double* h_err, const d
     return true;
 }
 
-extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const double* h_bits,
-                          int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t flags,
-                          int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
-                          int32_t* h_status) {
+namespace mgs {
+// The search over one sweep's tables.  `wait`, when not NULL, tells whether
+// ratio t's entries are on the host yet (the tables may still be on their way):
+// wait(ctx, t, 1) returns once they are, wait(ctx, t, 0) returns at once, 1
+// while they are not; MGS_OK means they are, anything else is the search's
+// error.
+int search_tables(const mgs_sweep_desc* d, const double* h_err, const double* h_bits, int64_t budget_bits,
+                  int32_t size_mode, int32_t threads, int32_t flags, int32_t* h_best_t, uint8_t* h_best_bits,
+                  double* h_obj, int64_t* h_used, int32_t* h_status, int (*wait)(void*, int, int), void* wait_ctx) {
     if (!d || !d->h_k || !d->h_bits || !h_err || !h_bits || !h_best_t || !h_best_bits || !h_obj ||
         !h_used)
         return MGS_EINVAL;
@@ -851,6 +858,25 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
         kmax = std::max(kmax, d->h_k[t]);
     }
     const int64_t gmaxn = (kmax + G - 1) / G;
+    // ratio t's entries are on the host (waited for once, by any thread)
+    std::unique_ptr<std::atomic<int>[]> landed(new std::atomic<int>[T]);
+    for (int t = 0; t < T; ++t) landed[t].store(wait ? 0 : 1, std::memory_order_relaxed);
+    std::atomic<int> wait_rc{MGS_OK};
+    auto wait_ratio = [&](int t) {
+        if (landed[t].load(std::memory_order_acquire)) return;
+        const int rc = wait(wait_ctx, t, 1);
+        if (rc != MGS_OK) wait_rc.store(rc);
+        landed[t].store(1, std::memory_order_release);
+    };
+    // without blocking: true once ratio t is on the host (or failed)
+    auto poll_ratio = [&](int t) {
+        if (landed[t].load(std::memory_order_acquire)) return true;
+        const int rc = wait(wait_ctx, t, 0);
+        if (rc == 1) return false;
+        if (rc != MGS_OK) wait_rc.store(rc);
+        landed[t].store(1, std::memory_order_release);
+        return true;
+    };
     int b8 = -1;
     for (int i = 0; i < nb; ++i)
         if (d->h_bits[i] == 8) b8 = i;
@@ -892,6 +918,7 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
     int t_spec = -1;
     for (int i = T - 1; i >= 0 && t_spec < 0; --i) {
         const int t = by_k[i];
+        wait_ratio(t);
         const int64_t k = d->h_k[t], ng = (k + G - 1) / G;
         int64_t s8 = 0;
         bool ok = true;
@@ -920,9 +947,9 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
     int spec_rc = MGS_EINVAL;  // the speculative solve: status, loss, size
     double spec_obj = 0;
     int64_t spec_used = 0;
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
-    for (int i = 0; i < T; ++i) {
-        const int t = items[i];
+    // per ratio: the checks, the doubled-8-bit test and the LP bound (the
+    // speculative ratio is solved exactly as well)
+    auto process = [&](int t) {
         h_obj[t] = std::numeric_limits<double>::quiet_NaN();
         h_used[t] = 0;
         const int64_t k = d->h_k[t];
@@ -930,7 +957,7 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
         const int64_t ncls = (int64_t)C * ng;
         if (ncls == 0) {
             state[t] = MGS_SEARCH_SKIPPED;
-            continue;
+            return;
         }
         // the all-8-bit size from the 8-bit column alone; every value of the
         // ratio is checked by the bound's pass over the options, or by a pass
@@ -954,12 +981,12 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
             for (int64_t cls = 0; cls < ncls && ok; ++cls) ok = f(cls, o);
             if (ok) {
                 state[t] = MGS_SEARCH_SKIPPED;
-                continue;
+                return;
             }
         }
         if (!ok) {
             st[t] = MGS_EINVAL;
-            continue;
+            return;
         }
         if (t == t_spec) {
             Mckp m(filler(t), ncls, nb, budget_bits);
@@ -972,7 +999,7 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
                 choice[t].resize(ncls);
                 spec_rc = m.exact(choice[t].data(), &spec_obj, &spec_used);
             }
-            continue;
+            return;
         }
         static thread_local Mckp wk;
         wk.rebind(filler(t), ncls, nb, budget_bits);
@@ -981,7 +1008,42 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
         else st[t] = rc;
         lb[t] = wk.lower_bound();
         lbtol[t] = wk.tol;
+    };
+    if (!wait) {
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+        for (int i = 0; i < T; ++i) process(items[i]);
+    } else {
+        // tables still arriving: the speculative ratio (already on the host,
+        // the pick above waited for it) on a thread of its own at once; one
+        // thread polls the other ratios and hands each to the pool as it lands
+        std::thread spec;
+        int first = 0;
+        if (t_spec >= 0) {
+            spec = std::thread([&] { process(t_spec); });
+            first = 1;
+        }
+        std::vector<int> pending(items.begin() + first, items.end());
+#pragma omp parallel num_threads(nthr)
+#pragma omp single
+        while (!pending.empty() && wait_rc.load() == MGS_OK) {
+            bool any = false;
+            for (size_t j = 0; j < pending.size();) {
+                const int t = pending[j];
+                if (!poll_ratio(t)) {
+                    ++j;
+                    continue;
+                }
+#pragma omp task firstprivate(t)
+                process(t);
+                pending[j] = pending.back();
+                pending.pop_back();
+                any = true;
+            }
+            if (!any) std::this_thread::yield();
+        }
+        if (spec.joinable()) spec.join();
     }
+    if (wait_rc.load() != MGS_OK) return wait_rc.load();
     for (int t = 0; t < T; ++t)
         if (st[t] != MGS_OK) return st[t];
     // ---- exact solves: the ratio of least lower bound first, then (in
@@ -1047,6 +1109,16 @@ extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const do
     const int64_t ng = (d->h_k[best] + G - 1) / G;
     for (int64_t cls = 0; cls < (int64_t)C * ng; ++cls) h_best_bits[cls] = d->h_bits[choice[best][cls]];
     return MGS_OK;
+}
+
+}  // namespace mgs
+
+extern "C" int mgs_search(const mgs_sweep_desc* d, const double* h_err, const double* h_bits,
+                          int64_t budget_bits, int32_t size_mode, int32_t threads, int32_t flags,
+                          int32_t* h_best_t, uint8_t* h_best_bits, double* h_obj, int64_t* h_used,
+                          int32_t* h_status) {
+    return mgs::search_tables(d, h_err, h_bits, budget_bits, size_mode, threads, flags, h_best_t, h_best_bits,
+                              h_obj, h_used, h_status, nullptr, nullptr);
 }
 
 // ------------------------------------------------------------- hierarchical solver

@@ -74,6 +74,7 @@ SIGNATURES = {
     "mgs_ilp_solve": (ct.c_int, [P, P, I64, I32, I64, P, P, P]),
     "mgs_size_table": (ct.c_int, [P, P, I64, I32, P, I32, P]),
     "mgs_search": (ct.c_int, [P, P, P, I64, I32, I32, I32, P, P, P, P, P]),
+    "mgs_search_streamed": (ct.c_int, [P, P, P, I64, I32, I32, I32, P, P, P, P, P, P]),
     "mgs_ilp_hierarchical": (ct.c_int, [P, P, I32, I64, I32, P, I64, P, P, P, P, P]),
     "mgs_search_calibrated": (ct.c_int, [P, P, P, I64, I32, I32, I32, P, P, P, P, P, P]),
 }
@@ -503,14 +504,22 @@ SEARCH_SOLVED, SEARCH_SKIPPED, SEARCH_INFEASIBLE, SEARCH_PRUNED, SEARCH_UNCONVER
 
 
 def search(N: int, C: int, k, G: int, bits, err: np.ndarray, bits_table: np.ndarray, budget_bits: int,
-           size_mode: int = 0, threads: int = 0, solve_all: bool = False):
+           size_mode: int = 0, threads: int = 0, solve_all: bool = False, events=None):
     """Reserve-ratio loop + exact ILP over host copies of a sweep's tables.
 
     Returns dict(best_t, best_bits u8[C][ng], obj f64[T], used i64[T], status i32[T]);
     best_t is -1 when no ratio is admissible.  Without ``solve_all`` ratios whose LP
-    bound exceeds the best optimum are not solved (status SEARCH_PRUNED).
+    bound exceeds the best optimum are not solved (status SEARCH_PRUNED).  With
+    ``events`` (one torch.cuda.Event per ratio, recorded after that ratio's table
+    slices were copied into ``err`` / ``bits_table``, which must then be the host
+    buffers themselves: no copy is made) the search starts while the copies run
+    (mgs_search_streamed).
     """
     d = sweep_desc(N, C, k, G, bits)
+    if events is not None:
+        for a in (err, bits_table):
+            if a.dtype != np.float64 or not a.flags.c_contiguous:
+                raise ValueError("streamed tables are read in place: contiguous float64 host buffers")
     err = np.ascontiguousarray(err, dtype=np.float64)
     bt = np.ascontiguousarray(bits_table, dtype=np.float64)
     T = d.T
@@ -521,9 +530,17 @@ def search(N: int, C: int, k, G: int, bits, err: np.ndarray, bits_table: np.ndar
     obj = np.empty(T, dtype=np.float64)
     used = np.empty(T, dtype=np.int64)
     status = np.empty(T, dtype=np.int32)
-    code = lib().mgs_search(ct.byref(d), _np_ptr(err), _np_ptr(bt), int(budget_bits), size_mode, threads,
-                            SEARCH_ALL if solve_all else 0, ct.byref(best_t), _np_ptr(best_bits),
-                            _np_ptr(obj), _np_ptr(used), _np_ptr(status))
+    if events is None:
+        code = lib().mgs_search(ct.byref(d), _np_ptr(err), _np_ptr(bt), int(budget_bits), size_mode, threads,
+                                SEARCH_ALL if solve_all else 0, ct.byref(best_t), _np_ptr(best_bits),
+                                _np_ptr(obj), _np_ptr(used), _np_ptr(status))
+    else:
+        if len(events) != T:
+            raise ValueError(f"one event per ratio: {len(events)} events for {T} ratios")
+        evs = (ct.c_void_p * T)(*[int(e.cuda_event) for e in events])
+        code = lib().mgs_search_streamed(ct.byref(d), _np_ptr(err), _np_ptr(bt), int(budget_bits), size_mode,
+                                         threads, SEARCH_ALL if solve_all else 0, ct.byref(best_t),
+                                         _np_ptr(best_bits), _np_ptr(obj), _np_ptr(used), _np_ptr(status), evs)
     if code not in (OK, EINFEASIBLE):
         _check(code, "mgs_search")
     t = best_t.value

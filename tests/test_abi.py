@@ -119,6 +119,15 @@ def test_host_solvers_reject_bad_arguments():
     assert calib(tol=1000001) == mgs.EINVAL
     assert calib(iters=0) == mgs.EINVAL
 
+    # the streamed search checks its events before it waits for any
+    res = [np.zeros(1), np.zeros(1, np.int64), np.zeros(1, np.int32)]
+
+    def streamed(events):
+        return L.mgs_search_streamed(ct.byref(d), P(tab), P(tab), 100, 0, 1, 0, ct.byref(bt), P(ob),
+                                     *[P(x) for x in res], events)
+    assert streamed(None) == mgs.EINVAL
+    assert streamed((ct.c_void_p * 1)(None)) == mgs.EINVAL
+
 
 def test_graph_calls_reject_null_handles():
     L = mgs.lib()

@@ -195,3 +195,40 @@ def test_search_parity_served_jobs(torch, orc):
         kt = kept[offs[r.best_t]:offs[r.best_t + 1]]
         oc, _, _ = orc.quantize(attr, kt, G, b["best_bits"])
         assert np.array_equal(r.codes, oc), job.job_id
+
+
+def test_search_streamed_equals_search(torch):
+    """mgs_search_streamed, started while the tables are still being copied
+    ratio by ratio (copy stream, one event per ratio, in the order the search
+    reads them), returns exactly what mgs_search returns on the finished
+    copy: the medium workload's GPU tables."""
+    w = synth.workload("medium")
+    a, i = w.make()
+    attr, imp = dev(torch, a), dev(torch, i)
+    k = w.k
+    kept = mgs.prune_select(imp, k)
+    tab = mgs.quant_sweep(attr, imp, kept, k, w.group, w.bits)
+    torch.cuda.synchronize()
+    T = len(k)
+    budget = w.n * w.channels * 32 // 30
+    want = mgs.search(w.n, w.channels, k, w.group, w.bits, host(tab["err"]), host(tab["bits"]), budget)
+    err_h = torch.empty(tab["err"].shape, dtype=torch.float64, pin_memory=True)
+    bits_h = torch.empty(tab["bits"].shape, dtype=torch.float64, pin_memory=True)
+    err_h.fill_(np.nan)
+    bits_h.fill_(np.nan)
+    cs = torch.cuda.Stream()
+    events = [torch.cuda.Event() for _ in range(T)]
+    order = [0] + list(range(T - 1, 0, -1))  # increasing k first, then decreasing
+    with torch.cuda.stream(cs):
+        for t in order:
+            err_h[t].copy_(tab["err"][t], non_blocking=True)
+            bits_h[t].copy_(tab["bits"][t], non_blocking=True)
+            events[t].record(cs)
+    got = mgs.search(w.n, w.channels, k, w.group, w.bits, err_h.numpy(), bits_h.numpy(), budget,
+                     events=events)
+    torch.cuda.synchronize()
+    assert got["best_t"] == want["best_t"]
+    assert np.array_equal(got["best_bits"], want["best_bits"])
+    assert np.array_equal(got["status"], want["status"])
+    assert np.array_equal(got["used"], want["used"])
+    assert np.array_equal(got["obj"], want["obj"], equal_nan=True)
