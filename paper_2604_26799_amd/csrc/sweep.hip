@@ -30,6 +30,9 @@
 //      leaves the code unchanged (it is absorbed by Z or rounds to 0).
 //      fl(fl(x/S) + Z) is then one fma(x/R, 2^b, Z).  Groups that fail the
 //      test (R < 2^(bmax - 126)) use the literal division per element.
+//      x / R itself takes one reciprocal per group and two corrections by
+//      the FMA remainder per element, which give the correctly rounded
+//      quotient (see the quotients of the kernel).
 //   2. round(clamp(t, 0, 2^b - 1)) == clamp(fl(t + 2^23), 2^23, 2^23 + 2^b - 1)
 //      - 2^23: adding 2^23 rounds any t in [0, 2^23) to an integer
 //      half-even, the clamp bounds are integers and fl() is monotone.  With
@@ -518,11 +521,22 @@ void sweep_kernel(SweepParams p) {
             if constexpr (CHUNKED) {
                 for (int ch = nchunk - 1; ch >= 0; --ch) gather(ch);  // ends holding chunk 0
             } else {
+                // every load issued before the first is used: elements past n
+                // hold index 0, an in-bounds read of row[0] that is dropped.
+                // The opaque copy keeps each index a 32-bit register (a 64-bit
+                // offset per element held across channels costs registers).
+                const global_ptr<const float> rowg = (global_ptr<const float>)row;
+#pragma unroll
+                for (int i = 0; i < EPT; ++i) {
+                    int32_t id = ids[i];
+                    asm volatile("" : "+v"(id));
+                    xv[i] = rowg[id];
+                }
 #pragma unroll
                 for (int i = 0; i < EPT; ++i) {
                     float x = 0.0f;
                     if (i * NT + tid < n) {
-                        x = row[ids[i]];
+                        x = xv[i];
                         const float w = wv[i];
                         bad |= (uint32_t)(!finite_f32(x) || !finite_f32(w));
                         mn = fminf(mn, x);
@@ -597,11 +611,34 @@ void sweep_kernel(SweepParams p) {
             // 2^-b, and the terms are rescaled by 2^(2E) in FP64.
             const int E = fast ? (int)((__float_as_uint(R) >> 23) & 0xFFu) - 127 : 0;
             const double esc = ldexp(1.0, 2 * E);
+            // u = x / R, correctly rounded, without a division per element:
+            // with Rs = R * 2^-E in [1, 2) and y = RN(1 / Rs), q = RN(xs * y)
+            // is within 1.5 ulp of xs / Rs; one correction by the exact FMA
+            // remainder xs - Rs * q makes it faithful, and a second one the
+            // correctly rounded quotient (Markstein's theorem: y within half an
+            // ulp of 1 / Rs, q within one ulp of xs / Rs).  The remainders are
+            // exact while |xs| >= 2^-100; below that both quotients are under
+            // 2^-100 in magnitude, far too small to move fma(u, 2^b, Z) off Z
+            // (|Z| >= 1) or, for Z = 0, t + 2^23 off 2^23, so the codes agree.
+            const float Rs = ldexpf(R, -E);
+            const float yr = fast ? 1.0f / Rs : 0.0f;
             auto quotients = [&]() {
 #pragma unroll
                 for (int i = 0; i < EPT; ++i) {
-                    u[i] = fast ? xv[i] / R : 0.0f;
-                    xv[i] = ldexpf(xv[i], -E);
+                    const float xs = ldexpf(xv[i], -E);
+                    float q = 0.0f;
+                    if (fast) {
+                        q = xs * yr;
+                        float r = __builtin_fmaf(-Rs, q, xs);
+                        q = __builtin_fmaf(r, yr, q);
+                        r = __builtin_fmaf(-Rs, q, xs);
+                        q = __builtin_fmaf(r, yr, q);
+                    }
+                    u[i] = q;
+                    xv[i] = xs;
+                    // one element at a time: the next one starts after this
+                    // quotient (interleaving them all costs registers)
+                    if (i + 1 < EPT) asm volatile("" : "+v"(u[i]), "+v"(xv[i + 1]));
                 }
             };
             quotients();

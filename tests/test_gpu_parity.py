@@ -146,6 +146,73 @@ def test_sweep_adversarial(torch, orc, G):
     assert_tables(got, want, hist=True, G=G)
 
 
+def quotient_tie_scene(G, bits, C, seed):
+    """Channels whose values put x / S_b + Z_b on a rounding tie (a half
+    integer) or a few ulps away from one, for every listed b, plus the group's
+    min and max; the rest of the group uniform in [min, max]."""
+    rng = np.random.default_rng(seed)
+    f32 = np.float32
+    attr = np.empty((C, G), f32)
+    for c in range(C):
+        mn, mx = f32(-rng.uniform(0.01, 50.0)), f32(rng.uniform(0.01, 50.0))
+        if c % 3 == 2:  # far from zero with a narrow range
+            mn, mx = f32(1000.0 + rng.uniform(0, 1)), f32(1003.0 + rng.uniform(0, 1))
+        R = f32(mx - mn)
+        vals = [mn, mx]
+        for b in bits:
+            P = f32(2.0 ** b)
+            S = f32(R / P)
+            Z = f32(np.rint(P - f32(mx / S)))
+            for j in rng.integers(0, 2 ** b, size=90):
+                x = f32(f32(f32(j + 0.5) - Z) * S)  # x / S close to the tie j + 0.5 - Z
+                for step in range(-3, 4):
+                    y = x
+                    for _ in range(abs(step)):
+                        y = np.nextafter(y, f32(np.inf) if step > 0 else f32(-np.inf))
+                    if mn <= y <= mx:
+                        vals.append(y)
+        vals = np.array(vals[:G], f32)
+        fill = rng.uniform(float(mn), float(mx), size=G - len(vals)).astype(f32)
+        row = np.concatenate([vals, np.clip(fill, mn, mx)])
+        rng.shuffle(row)
+        attr[c] = row
+    imp = rng.uniform(0.1, 2.0, size=G).astype(f32)
+    return attr, imp
+
+
+def literal_codes(x, b):
+    """The FP32 quantizer of one group, literally (numpy FP32 operations are
+    correctly rounded); `nudge` moves x / R one ulp up before the scaling."""
+    f32 = np.float32
+    mn, mx = x.min(), x.max()
+    R, P = f32(mx - mn), f32(2.0 ** b)
+    S = f32(R / P)
+    Z = f32(np.rint(P - f32(mx / S)))
+    u = (x / R).astype(f32)
+    out = []
+    for uu in (u, np.nextafter(u, f32(np.inf))):
+        t = (uu * P).astype(f32) + Z  # uu * P is exact: P is a power of two
+        out.append(np.rint(np.clip(t, f32(0), P - 1)))
+    return out
+
+
+def test_sweep_quotient_ties(torch, orc):
+    """Codes on and next to rounding ties for every bit-width: the kernel's
+    x / R (one reciprocal per group, two FMA corrections per element) must be
+    the correctly rounded quotient, else codes here move.  The scene is
+    checked to be sensitive: moving x / R by one ulp changes codes."""
+    G, C = 4096, 6
+    bits = [1, 3, 8, 12, 16]
+    attr, imp = quotient_tie_scene(G, bits, C, seed=77)
+    moved = sum(int(np.sum(a != b)) for c in range(C) for bb in bits for a, b in [literal_codes(attr[c], bb)])
+    assert moved > 100, moved
+    k = np.array([G], np.int64)
+    kept = np.arange(G, dtype=np.int32)
+    want = orc.quant_sweep(attr, imp, kept, k, G, bits, want_hist=True)
+    got = gpu_sweep(torch, attr, imp, kept, k, G, bits, hist=True)
+    assert_tables(got, want, hist=True, G=G)
+
+
 def test_sweep_every_shape_identical(torch, orc):
     """Launch shapes (threads, elements per thread, LDS capacity, channels per
     tile, chunked, persistent grid) change nothing beyond the summation order
