@@ -373,7 +373,9 @@ void sweep_kernel(SweepParams p) {
 
     const int tid = threadIdx.x;
     const int lane = tid & (MGS_WAVE - 1);
-    const int wave = tid / MGS_WAVE;
+    // the same in every lane of a wavefront: scalar, so that addresses made
+    // from it are never held (or spilled) per lane
+    const int wave = __builtin_amdgcn_readfirstlane(tid / MGS_WAVE);
 
     const double* __restrict__ lgt = p.lgtab;
     const double* __restrict__ lft = p.lgtab + (p.lgtab_max + 1);
@@ -459,6 +461,7 @@ void sweep_kernel(SweepParams p) {
         const int n = (int)(krem < sc->G ? krem : sc->G);
         const int32_t* J = sc->kept + sc->koff[t] + j0;
         const int nb = sc->nb;
+        const int my_bl = tid < nb ? (int)sc->bl[tid] : 0;  // this thread's bit-width (tid < nb)
 
         // ---- per-element state in registers.  The kept indices and the
         // weights are the same for every channel of the tile: they are
@@ -480,11 +483,16 @@ void sweep_kernel(SweepParams p) {
         }
         // the first batch's bins are cleared before the barrier of the
         // channel's min/max (the later batches clear their own)
+        // (t0: an opaque copy of tid, so that the start addresses are made
+        // afresh here rather than held, or spilled, across the channel loop;
+        // the same below)
         auto clear_batch = [&](int bt) {
             const int words = p.batch_words[bt];
+            int t0 = tid;
+            asm volatile("" : "+v"(t0));
             uint4* h4 = reinterpret_cast<uint4*>(hist);
-            for (int w = tid; w < (words >> 2); w += NT) h4[w] = make_uint4(0u, 0u, 0u, 0u);
-            for (int w = (words & ~3) + tid; w < words; w += NT) hist[w] = 0u;
+            for (int w = t0; w < (words >> 2); w += NT) h4[w] = make_uint4(0u, 0u, 0u, 0u);
+            for (int w = (words & ~3) + t0; w < words; w += NT) hist[w] = 0u;
         };
         for (int c = c0; c < c1; ++c) {
             clear_batch(0);
@@ -589,15 +597,17 @@ void sweep_kernel(SweepParams p) {
 
             // ---- per-b scale and zero point (literal FP32 definition)
             if (tid < nb) {
-                float P = ldexpf(1.0f, sc->bl[tid]);
+                float P = ldexpf(1.0f, my_bl);
                 float S = R / P;
                 float Z = 0.0f;
                 if (S != 0.0f) {
                     float r = mx / S;
                     Z = __builtin_rintf(P - r);
                 }
-                prmS[tid] = S;
-                prmZ[tid] = Z;
+                int t0 = tid;
+                asm volatile("" : "+v"(t0));
+                prmS[t0] = S;
+                prmZ[t0] = Z;
             }
             // a range that underflows at some b (S_b = 0; S only shrinks with b)
             const bool anyzero = R / ldexpf(1.0f, sc->bmax) == 0.0f;
