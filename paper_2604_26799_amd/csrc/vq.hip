@@ -7,23 +7,34 @@
 // in FP64 over d in order; ties -> smallest j.
 //
 // Method.  argmin_j ||x - c_j||^2 = argmin_j s_j with s_j = ||c_j||^2 - 2 x.c_j.
-//   1. Scores s~_j from BF16 MFMA (v_mfma_f32_32x32x16_bf16, FP32
-//      accumulation).  The codeword tile is the A operand (32 codewords x 16
-//      dims), the X tile the B operand (16 dims x 32 rows), so each lane owns
-//      one row and 16 codewords of every 32x32 output tile and keeps its
-//      running minimum without cross-lane work.  ||c_j||^2 enters as two
-//      extra K columns (its BF16 high and low parts) against constant 1s in X.
-//   2. Error bound per row: |s~_j - s_j| <= E_i with
-//        E_i = 2(2u+u^2)|x_i| cmax + 2^-15 cmax^2 + g (2.02 |x_i| cmax + 1.01 cmax^2)
-//      (u = 2^-8 BF16 rounding, g = (D+3) 2^-23 for any FP32 accumulation
-//      order).  The exact winner then satisfies s~_j <= min s~ + 2 E_i; a
-//      small FP64 slack 2 delta_i also admits the winner of the FP64
-//      definition when exact distances tie within FP64 rounding.
-//   3. Two passes over the codebook.  Pass 1 keeps each lane's minimum
-//      score; the row minimum m (both lanes of the row) fixes the threshold
-//      m + T_i.  Pass 2 recomputes the scores and records, per lane, the
-//      tiles holding scores under the threshold with a mask of those
-//      codewords (up to 8 tiles per lane); the row's candidates are then
+//   1. Scores s~_j from FP16 MFMA (v_mfma_f32_32x32x16_f16, FP32
+//      accumulation) on the scaled vectors sigma x and sigma c, sigma a power
+//      of two that puts the largest codeword norm cmax in [2^6, 2^7), so the
+//      scores are sigma^2 s_j.  The codeword tile is the A operand (32
+//      codewords x 16 dims), the X tile the B operand (16 dims x 32 rows), so
+//      each lane owns one row and 16 codewords of every 32x32 output tile and
+//      keeps its running minimum without cross-lane work.  ||sigma c_j||^2
+//      enters as two extra K columns (its FP16 high and low parts) against
+//      constant 1s in X.  A row with a scaled value of 2^15 or more (outside
+//      FP16) goes to the exact scan of step 3.
+//   2. Error bound per row, in scaled units (xs = sigma |x_i|, cs = sigma cmax):
+//        E_i = (2u+u^2) xs 2cs + a(1+u) sqrt(D)(2cs + xs) + D a^2 + 2u^2 cs^2 + 2a
+//              + g (2.02 xs cs + 1.01 cs^2)
+//      (u = 2^-11 FP16 rounding, a = 2^-14 for values below the FP16 normal
+//      range whether kept or flushed, g = (D+3) 2^-23 for any FP32
+//      accumulation order).  The exact winner then satisfies
+//      s~_j <= min s~ + 2 E_i; a small FP64 slack 2 delta_i also admits the
+//      winner of the FP64 definition when exact distances tie within FP64
+//      rounding.
+//   3. One pass over the codebook.  Each lane keeps its running minimum m of
+//      the scores it has seen and records the tiles whose smallest score is
+//      within T_i of it, with a mask of their codewords scoring at most
+//      m + T_i (m taken after the tile; up to 8 tiles per lane).  A tile that
+//      lowers m so far that m + T_i falls below the previous minimum clears
+//      the list: every earlier tile scored at least that previous minimum, so
+//      above the final threshold (the row minimum only falls), and cannot
+//      hold the winner.  Thresholds only fall, so each mask holds every
+//      codeword under the final threshold.  The row's candidates are then
 //      re-scored with the FP64 definition (same operation order) and the
 //      smallest (distance, index) wins.  Rows with more candidate tiles than
 //      slots go to an exact FP64 full scan.
@@ -37,14 +48,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <type_traits>
 
 #include "common.h"
 
 namespace mgs {
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int VQ_WAVES = 4;
@@ -61,7 +71,7 @@ struct VqArgs {
     double* dist;
     int64_t* nfb_out;
     mgs_status_block* status;
-    __bf16* cbp;          // [Kpad][KP] prepared codebook (-2c, ||c||^2 hi, lo, 0 pad)
+    _Float16* cbp;        // [Kpad][KP] prepared codebook (-2 sigma c, ||sigma c||^2 hi, lo, 0 pad)
     uint32_t* cmax_bits;  // max codeword norm, FP32 bits (rounded up)
     uint32_t* fb_count;
     int32_t* fb_list;
@@ -70,55 +80,33 @@ struct VqArgs {
     int32_t xvec;         // D % 4 == 0 and x 16-byte aligned: rows load as float4
 };
 
-// Prepared codebook and the codeword-norm maximum (the status word, the
-// maximum and the fallback counter are cleared before this kernel).  One
-// thread per codeword; the loops run over the compile-time row width, so the
-// codeword's loads are all issued before use and its row is written as
-// 16-byte units.
-template <int KS>
-__global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
-    constexpr int KP = 16 * KS;
+// The scale of the MFMA operands: 2^(6 - e) for cmax in [2^e, 2^(e+1)), so
+// that |sigma c_j| < 2^7 and ||sigma c_j||^2 < 2^14 (1 for a zero or
+// non-finite maximum).
+__device__ __forceinline__ float vq_scale(float cm) {
+    if (!(cm > 0.0f) || !finite_f32(cm)) return 1.0f;
+    int ex;
+    (void)frexpf(cm, &ex);  // cm = m 2^ex, m in [0.5, 1)
+    return ldexpf(1.0f, min(max(7 - ex, -126), 126));
+}
+
+// The codeword-norm maximum, rounded up (the status word, the maximum and
+// the fallback counter are cleared before this kernel).  One thread per
+// codeword.
+__global__ __launch_bounds__(256) void vq_norm_kernel(VqArgs a) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     float nrm = 0.0f;  // FP32 bits of non-negative floats order as unsigned ints
-    if (j < a.Kpad) {
-        // unit u of codeword j: chunk j / 64, unit-major inside the chunk
-        bf16x8* row = (bf16x8*)(a.cbp + (int64_t)(j / VQ_CHUNK) * VQ_CHUNK * KP) + (j % VQ_CHUNK);
-        if (j >= a.K) {
-#pragma unroll
-            for (int u = 0; u < KP / 8; ++u) {
-                bf16x8 z;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) z[i] = (__bf16)(8 * u + i == a.D ? 1.0e30f : 0.0f);
-                row[u * VQ_CHUNK] = z;  // padding codewords score ~1e30 and are skipped
-            }
-        } else {
-            const float* c = a.cb + (int64_t)j * a.D;
-            float v[KP];
-#pragma unroll
-            for (int k = 0; k < KP; ++k) v[k] = k < a.D ? c[k] : 0.0f;
-            double n2 = 0.0;
-            bool bad = false;
-#pragma unroll
-            for (int k = 0; k < KP; ++k)
-                if (k < a.D) {
-                    bad |= !finite_f32(v[k]);
-                    n2 += (double)v[k] * (double)v[k];
-                }
-            const float hi = (float)(__bf16)(float)n2;
-            const float lo = (float)(n2 - (double)hi);
-#pragma unroll
-            for (int u = 0; u < KP / 8; ++u) {
-                bf16x8 w;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int k = 8 * u + i;
-                    w[i] = (__bf16)(k < a.D ? -2.0f * v[k] : k == a.D ? hi : k == a.D + 1 ? lo : 0.0f);
-                }
-                row[u * VQ_CHUNK] = w;
-            }
-            if (bad) atomicOr(&a.status->nonfinite, 1u);
-            nrm = (float)sqrt(n2) * (1.0f + 1.0e-6f);
+    if (j < a.K) {
+        const float* c = a.cb + (int64_t)j * a.D;
+        double n2 = 0.0;
+        bool bad = false;
+        for (int k = 0; k < a.D; ++k) {
+            const float v = c[k];
+            bad |= !finite_f32(v);
+            n2 += (double)v * (double)v;
         }
+        if (bad) atomicOr(&a.status->nonfinite, 1u);
+        nrm = (float)sqrt(n2) * (1.0f + 1.0e-6f);
     }
     // the block's largest norm, then one atomic per block (thousands of
     // atomics on one address serialise)
@@ -132,6 +120,46 @@ __global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
         for (int w = 1; w < (int)(blockDim.x / MGS_WAVE); ++w) m = max(m, red[w]);
         m = max(m, red[0]);
         atomicMax(a.cmax_bits, m);
+    }
+}
+
+// Prepared codebook: -2 sigma c and the high and low FP16 parts of
+// ||sigma c||^2 (FP64), zero padding; padding codewords (j >= K) are all
+// zero and masked in the main kernel.  One thread per codeword; the loops
+// run over the compile-time row width, so the codeword's loads are all issued
+// before use and its row is written as 16-byte units.
+template <int KS>
+__global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
+    constexpr int KP = 16 * KS;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.Kpad) return;
+    // unit u of codeword j: chunk j / 64, unit-major inside the chunk
+    f16x8* row = (f16x8*)(a.cbp + (int64_t)(j / VQ_CHUNK) * VQ_CHUNK * KP) + (j % VQ_CHUNK);
+    if (j >= a.K) {
+#pragma unroll
+        for (int u = 0; u < KP / 8; ++u) row[u * VQ_CHUNK] = f16x8{};
+        return;
+    }
+    const float sg = vq_scale(__uint_as_float(*a.cmax_bits));
+    const float* c = a.cb + (int64_t)j * a.D;
+    float v[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) v[k] = k < a.D ? c[k] * sg : 0.0f;  // exact power-of-two scaling
+    double n2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+        if (k < a.D) n2 += (double)v[k] * (double)v[k];
+    const _Float16 hi = (_Float16)(float)n2;
+    const _Float16 lo = (_Float16)(float)(n2 - (double)(float)hi);
+#pragma unroll
+    for (int u = 0; u < KP / 8; ++u) {
+        f16x8 w;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 8 * u + i;
+            w[i] = k < a.D ? (_Float16)(-2.0f * v[k]) : k == a.D ? hi : k == a.D + 1 ? lo : (_Float16)0.0f;
+        }
+        row[u * VQ_CHUNK] = w;
     }
 }
 
@@ -156,8 +184,8 @@ void vq_main_kernel(VqArgs a) {
     // two variables and every chunk step reads a fixed one, so the compiler
     // can tell that the copy into one buffer leaves the other alone and does
     // not wait for the copy before reading.
-    __shared__ __attribute__((aligned(16))) __bf16 cbs0[VQ_CHUNK * KP];
-    __shared__ __attribute__((aligned(16))) __bf16 cbs1[VQ_CHUNK * KP];
+    __shared__ __attribute__((aligned(16))) _Float16 cbs0[VQ_CHUNK * KP];
+    __shared__ __attribute__((aligned(16))) _Float16 cbs1[VQ_CHUNK * KP];
     // candidate tiles: tile index and the mask of the lane's codewords in it
     __shared__ int32_t cand_t[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
     __shared__ uint16_t cand_m[VQ_WAVES][VQ_ROWSETS][VQ_CAND][MGS_WAVE];
@@ -168,15 +196,18 @@ void vq_main_kernel(VqArgs a) {
     const int D = a.D, K = a.K;
     const int64_t row0 = (int64_t)blockIdx.x * VQ_ROWS + wave * (VQ_ROWSETS * 32);
 
-    // ---- B operands (the X rows), bound T per row
-    bf16x8 breg[VQ_ROWSETS][KS];
+    // ---- B operands (the scaled X rows), bound T per row
+    f16x8 breg[VQ_ROWSETS][KS];
     float T[VQ_ROWSETS];
+    bool big[VQ_ROWSETS];  // a scaled value outside FP16: exact scan
     uint32_t bad = 0;
     const float cm = __uint_as_float(*a.cmax_bits);
+    const float sg = vq_scale(cm);
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
         const int64_t r = row0 + rs * 32 + (lane & 31);
         float n2 = 0.0f;
+        bool bg = false;
         if (a.xvec) {
             // D % 4 == 0 and 16-byte aligned rows: every group of 4 dims is one
             // unconditional float4 load from an in-bounds address (row and
@@ -202,14 +233,15 @@ void vq_main_kernel(VqArgs a) {
                     float v = 0.0f;
                     if (r < a.N) {
                         if (k < D) {
-                            v = e;
-                            bad |= (uint32_t)!finite_f32(v);
-                            n2 += v * v;
+                            bad |= (uint32_t)!finite_f32(e);
+                            n2 += e * e;
+                            v = e * sg;
+                            bg |= !(fabsf(v) < 32768.0f);
                         } else if (k == D || k == D + 1) {
                             v = 1.0f;
                         }
                     }
-                    breg[rs][ks][i] = (__bf16)v;
+                    breg[rs][ks][i] = (_Float16)v;
                 }
         } else {
 #pragma unroll
@@ -220,34 +252,40 @@ void vq_main_kernel(VqArgs a) {
                     float v = 0.0f;
                     if (r < a.N) {
                         if (k < D) {
-                            v = a.x[r * D + k];
-                            bad |= (uint32_t)!finite_f32(v);
-                            n2 += v * v;
+                            const float e = a.x[r * D + k];
+                            bad |= (uint32_t)!finite_f32(e);
+                            n2 += e * e;
+                            v = e * sg;
+                            bg |= !(fabsf(v) < 32768.0f);
                         } else if (k == D || k == D + 1) {
                             v = 1.0f;
                         }
                     }
-                    breg[rs][ks][i] = (__bf16)v;
+                    breg[rs][ks][i] = (_Float16)v;
                 }
             }
         }
         n2 += __shfl_xor(n2, 32, MGS_WAVE);
-        const double xn = sqrt((double)n2) * (1.0 + 1.0e-5) + 1e-30;
-        const double u = 1.0 / 256.0;
+        big[rs] = (bg | (__shfl_xor((int)bg, 32, MGS_WAVE) != 0));
+        // the bound in scaled units (sigma is a power of two)
+        const double xs = (double)sg * (sqrt((double)n2) * (1.0 + 1.0e-5) + 1e-30);
+        const double cs = (double)sg * (double)cm;
+        const double u = 0x1p-11, aa = 0x1p-14, rd = sqrt((double)D);
         const double g = (double)(D + 3) * 0x1p-23;
-        const double E = 2.0 * (2.0 * u + u * u) * xn * cm + 0x1p-15 * (double)cm * cm +
-                         g * (2.02 * xn * cm + 1.01 * (double)cm * cm);
-        const double delta = 2.0 * (D + 2) * 0x1p-52 * (xn + cm) * (xn + cm);
-        const double scale = (double)cm * cm + 2.0 * xn * cm;
+        const double E = (2.0 * u + u * u) * xs * (2.0 * cs) + aa * (1.0 + u) * rd * (2.0 * cs + xs) +
+                         (double)D * aa * aa + 2.0 * u * u * cs * cs + 2.0 * aa +
+                         g * (2.02 * xs * cs + 1.01 * cs * cs);
+        const double delta = 2.0 * (D + 2) * 0x1p-52 * (xs + cs) * (xs + cs);
+        const double scale = cs * cs + 2.0 * xs * cs;
         T[rs] = (float)((2.0 * E + 2.0 * delta) * 1.0001 + 1.0e-6 * scale + 1e-30);
     }
     if (bad) atomicOr(&a.status->nonfinite, 1u);
 
-    float thr[VQ_ROWSETS];
+    float mrun[VQ_ROWSETS];  // running minimum of the lane's scores
     int cnt[VQ_ROWSETS];
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-        thr[rs] = INFINITY;
+        mrun[rs] = INFINITY;
         cnt[rs] = 0;
     }
 
@@ -255,7 +293,7 @@ void vq_main_kernel(VqArgs a) {
     // `dst`: wave w moves units [(i*VQ_WAVES + w)*64, +64) of the chunk; the
     // LDS base of each instruction is uniform over the wave.
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-    auto prefetch = [&](int c0, __bf16* dst) {
+    auto prefetch = [&](int c0, _Float16* dst) {
         constexpr int nunits = VQ_CHUNK * UNITS;  // Kpad is a whole number of chunks
         const char* src = (const char*)(a.cbp + (int64_t)c0 * KP);
 #pragma unroll
@@ -268,25 +306,23 @@ void vq_main_kernel(VqArgs a) {
         }
     };
     const int nchunks = a.Kpad / VQ_CHUNK;
-    // The two passes are one sequence of 2 * nchunks chunk steps q (pass 0:
-    // minimum score per lane; pass 1: codewords under the threshold); step q
-    // reads buffer q % 2 while the next chunk is copied into the other one.
-    auto chunk = [&](auto pass_tag, int q, const __bf16* cb_l, __bf16* other) {
-        constexpr bool pass0 = decltype(pass_tag)::value;
-        const int c0 = (pass0 ? q : q - nchunks) * VQ_CHUNK;
+    // Chunk step q reads buffer q % 2 while the next chunk is copied into the
+    // other one.
+    auto chunk = [&](int q, const _Float16* cb_l, _Float16* other) {
+        const int c0 = q * VQ_CHUNK;
         // the other buffer was last read before the barrier that ended the
-        // previous step: fill it with the next chunk (pass 1 restarts at
-        // chunk 0) while this one is processed
-        if (q + 1 < 2 * nchunks) prefetch(q + 1 == nchunks ? 0 : c0 + VQ_CHUNK, other);
+        // previous step: fill it with the next chunk while this one is
+        // processed
+        if (q + 1 < nchunks) prefetch(c0 + VQ_CHUNK, other);
         // scores of one 32-codeword tile for the wave's row sets; K steps
         // outer, row sets inner: consecutive MFMAs are independent.  Lane l
         // reads unit 2 ks + (l / 32) of codeword tile * 32 + l % 32: 512
         // contiguous bytes per half-wave
         auto scores = [&](int tile, f32x16 (&acc)[VQ_ROWSETS]) {
-            bf16x8 areg[KS];
+            f16x8 areg[KS];
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
-                areg[ks] = *(const bf16x8*)((const char*)cb_l +
+                areg[ks] = *(const f16x8*)((const char*)cb_l +
                                             (size_t)(((2 * ks + half) * VQ_CHUNK) + tile * 32 + (lane & 31)) * 16);
 #pragma unroll
             for (int rs = 0; rs < VQ_ROWSETS; ++rs) acc[rs] = f32x16{};
@@ -294,36 +330,41 @@ void vq_main_kernel(VqArgs a) {
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
                 for (int rs = 0; rs < VQ_ROWSETS; ++rs)
-                    acc[rs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(areg[ks], breg[rs][ks], acc[rs], 0, 0, 0);
+                    acc[rs] = __builtin_amdgcn_mfma_f32_32x32x16_f16(areg[ks], breg[rs][ks], acc[rs], 0, 0, 0);
         };
         auto epilogue = [&](int tile, const f32x16 (&acc)[VQ_ROWSETS]) {
             const int jbase = c0 + tile * 32;
 #pragma unroll
             for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-                if constexpr (pass0) {
-                    float tmin = acc[rs][0];
+                float sc[16];
 #pragma unroll
-                    for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
-                    thr[rs] = fminf(thr[rs], tmin);  // pass 0 keeps the lane minimum here
-                } else {
-                    float tmin = acc[rs][0];
-#pragma unroll
-                    for (int i = 1; i < 16; ++i) tmin = fminf(tmin, acc[rs][i]);
-                    if (tmin > thr[rs]) continue;  // most lane-tiles hold no candidate
-                    // sign bits of thr - s, shifted in by v_alignbit (element i
-                    // lands in bit 15 - i); s <= thr  <=>  thr - s >= 0 (an exact
-                    // zero difference is +0), so the mask is the complement
-                    uint32_t neg = 0;
+                for (int i = 0; i < 16; ++i) sc[i] = acc[rs][i];
+                if (jbase + 32 > K) {  // the codebook's last tile: padding codewords never count
 #pragma unroll
                     for (int i = 0; i < 16; ++i)
-                        neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(thr[rs] - acc[rs][i]), 31);
-                    const uint32_t bits = ~neg & 0xFFFFu;
-                    if (cnt[rs] < VQ_CAND) {
-                        cand_t[wave][rs][cnt[rs]][lane] = jbase;
-                        cand_m[wave][rs][cnt[rs]][lane] = (uint16_t)bits;
-                    }
-                    cnt[rs] += 1;  // a count past VQ_CAND marks the overflow
+                        if (jbase + 8 * (i >> 2) + 4 * half + (i & 3) >= K) sc[i] = INFINITY;
                 }
+                float tmin = sc[0];
+#pragma unroll
+                for (int i = 1; i < 16; ++i) tmin = fminf(tmin, sc[i]);
+                if (!(tmin <= mrun[rs] + T[rs])) continue;  // most lane-tiles hold no candidate
+                const float mo = mrun[rs];
+                mrun[rs] = fminf(mo, tmin);
+                const float thr = mrun[rs] + T[rs];
+                if (thr < mo) cnt[rs] = 0;  // no earlier tile can hold the winner
+                // sign bits of thr - s, shifted in by v_alignbit (element i
+                // lands in bit 15 - i); s <= thr  <=>  thr - s >= 0 (an exact
+                // zero difference is +0), so the mask is the complement
+                uint32_t neg = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(thr - sc[i]), 31);
+                const uint32_t bits = ~neg & 0xFFFFu;
+                if (cnt[rs] < VQ_CAND) {
+                    cand_t[wave][rs][cnt[rs]][lane] = jbase;
+                    cand_m[wave][rs][cnt[rs]][lane] = (uint16_t)bits;
+                }
+                cnt[rs] += 1;  // a count past VQ_CAND marks the overflow
             }
         };
         // software pipeline: the next tile's MFMAs are issued before this
@@ -355,32 +396,19 @@ void vq_main_kernel(VqArgs a) {
     prefetch(0, cbs0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    // step q reads buffer q % 2; each pass has its own code (no per-tile
-    // branch on the pass)
-    const std::integral_constant<bool, true> P0;
-    const std::integral_constant<bool, false> P1;
+    // step q reads buffer q % 2
     int q = 0;
     for (; q + 1 < nchunks; q += 2) {
-        chunk(P0, q, cbs0, cbs1);
-        chunk(P0, q + 1, cbs1, cbs0);
+        chunk(q, cbs0, cbs1);
+        chunk(q + 1, cbs1, cbs0);
     }
-    if (q < nchunks) chunk(P0, q++, cbs0, cbs1);
-    // end of pass 0: row minimum (the partner lane holds the other 16
-    // codewords of every tile) plus the bound
-#pragma unroll
-    for (int rs = 0; rs < VQ_ROWSETS; ++rs)
-        thr[rs] = fminf(thr[rs], __shfl_xor(thr[rs], 32, MGS_WAVE)) + T[rs];
-    if (q & 1) chunk(P1, q++, cbs1, cbs0);
-    for (; q + 1 < 2 * nchunks; q += 2) {
-        chunk(P1, q, cbs0, cbs1);
-        chunk(P1, q + 1, cbs1, cbs0);
-    }
+    if (q < nchunks) chunk(q, cbs0, cbs1);
 
     // ---- exact FP64 re-rank of the row's candidates (both lanes of the row)
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
         const int64_t r = row0 + rs * 32 + (lane & 31);
-        const int ovf = cnt[rs] > VQ_CAND;
+        const int ovf = cnt[rs] > VQ_CAND || big[rs];
         const int ovf_row = ovf | __shfl_xor(ovf, 32, MGS_WAVE);
         double best = INFINITY;
         int32_t bj = 0x7fffffff;
@@ -477,13 +505,13 @@ VqLayout vq_layout(int64_t N, int D, int K) {
     VqLayout L;
     L.KS = (D + 2 + 15) / 16;
     L.KP = 16 * L.KS;
-    // whole chunks: padding codewords score ~1e30 and never become candidates
+    // whole chunks: padding codewords are masked in the main kernel
     L.Kpad = (int)(((int64_t)K + VQ_CHUNK - 1) / VQ_CHUNK * VQ_CHUNK);
     size_t o = MGS_STATUS_BYTES;
     L.cmax = o;
     o += 256;
     L.cbp = o;
-    o += mgs_align_up(sizeof(__bf16) * (size_t)L.Kpad * L.KP, 256);
+    o += mgs_align_up(sizeof(_Float16) * (size_t)L.Kpad * L.KP, 256);
     L.fb = o;
     o += mgs_align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(N, 1), 256);
     L.total = o;
@@ -519,7 +547,7 @@ extern "C" int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float
     a.status = (mgs_status_block*)ws;
     a.cmax_bits = (uint32_t*)(ws + L.cmax);
     a.fb_count = (uint32_t*)(ws + L.cmax + 64);
-    a.cbp = (__bf16*)(ws + L.cbp);
+    a.cbp = (_Float16*)(ws + L.cbp);
     a.fb_list = (int32_t*)(ws + L.fb);
     a.N = N;
     a.D = D;
@@ -531,6 +559,7 @@ extern "C" int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float
     if (rc) return rc;
     rc = mgs_fill<uint32_t>(a.cmax_bits, 64, 0u, s);              // norm maximum + fallback count
     if (rc) return rc;
+    hipLaunchKernelGGL(vq_norm_kernel, dim3((K + 255) / 256), dim3(256), 0, s, a);
     const dim3 pgrid((L.Kpad + 255) / 256);
     switch (L.KS) {
         case 1: hipLaunchKernelGGL(vq_prep_kernel<1>, pgrid, dim3(256), 0, s, a); break;

@@ -500,6 +500,30 @@ def test_vq_duplicates_and_self(torch, orc):
     assert (host(idx)[400:450] == np.arange(50)).all()
 
 
+@pytest.mark.parametrize("case", ["x_far_larger", "x_far_smaller", "huge_codebook"])
+def test_vq_operand_ranges(torch, orc, case):
+    """The MFMA operands are sigma x and sigma c in FP16 with sigma set by the
+    largest codeword norm: rows far larger than the codebook leave FP16 (exact
+    scan), rows far smaller fall below its normal range (covered by the
+    bound), and a huge codeword sets a tiny scale for the others."""
+    rng = np.random.default_rng(31)
+    cb = rng.laplace(0, 0.5, (700, 36)).astype(np.float32)
+    x = rng.laplace(0, 0.5, (2000, 36)).astype(np.float32)
+    if case == "x_far_larger":
+        x[::7] *= np.float32(1e6)
+    elif case == "x_far_smaller":
+        x[::3] *= np.float32(1e-7)
+    else:
+        cb[5] = np.float32(1e30)
+        x[:50] = cb[rng.integers(0, 700, 50)] + np.float32(1e-3)
+    idx, dist, nfb = mgs.vq_assign(dev(torch, x), dev(torch, cb))
+    want_i, want_d = orc.vq_assign(x, cb)
+    np.testing.assert_array_equal(host(idx), want_i)
+    np.testing.assert_array_equal(host(dist), want_d)
+    if case == "x_far_larger":
+        assert int(host(nfb)[0]) >= x[::7].shape[0]  # every scaled-out row took the exact scan
+
+
 def test_vq_workload_sampled(torch, orc):
     """N=3e6 x 36 dims, K=4096 (the benchmarked launch); a 20k-row sample checked
     bit-exactly against the FP64 brute force, plus rows that equal codewords."""
