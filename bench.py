@@ -36,7 +36,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK = 8.0e12             # bytes/s, MI355X HBM3E
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-operations/s: 256 CUs x 64 lanes x 2.4 GHz
-MFMA_BF16_PEAK = 2.5e15       # dense bf16 FLOP/s
+MFMA_F16_PEAK = 2.5e15        # dense fp16 (and bf16) FLOP/s
 # VALU instructions one evaluation needs at the least: the quantize FMA, the
 # clamp, the round, the code's bin address, (q - Z) * S, the difference, its
 # square and the weighted accumulation -- 6 to 9 by instruction counting; the
@@ -292,7 +292,7 @@ def main():
         },
         "paper_context": dict(PAPER_CONTEXT, this_sweep_s=sweep_avg_s, this_ilp_s=med["ilp"] * 1e-3),
         "vq": {"tflops_alg": vq_flops / (med["vq"] * 1e-3) / 1e12,
-               "mfma_frac": vq_flops / (med["vq"] * 1e-3) / MFMA_BF16_PEAK,
+               "mfma_frac": vq_flops / (med["vq"] * 1e-3) / MFMA_F16_PEAK,
                "fallback_rows": int(nfb.item())},
     }
     out["search_variants"] = search_variants(mgs, w, k, G, err_h.numpy(), bits_h.numpy(), budget_bits)
