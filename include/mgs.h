@@ -375,7 +375,10 @@ int mgs_graph_destroy(void* graph);
  * the budget, solve, and choose the ratio with the smallest loss (ties:
  * larger k_t).  Ratios are solved in increasing order of their LP lower
  * bound and a ratio whose bound exceeds the best optimum found is not solved
- * (it cannot win); flags & MGS_SEARCH_ALL solves every admissible ratio.
+ * (it cannot win); so is a ratio whose Lagrangian bound at the multiplier of
+ * the smallest ratio that passes the doubled-8-bit test exceeds the loss of
+ * that ratio's greedy allocation.  flags & MGS_SEARCH_ALL solves every
+ * admissible ratio.
  * Writes h_best_t, the chosen bit-widths h_best_bits[C][ceil(k_best / G)]
  * (caller sizes it for the largest k), per ratio h_obj[t] / h_used[t] (NaN / 0
  * unless solved) and, if h_status is not NULL, h_status[t] (MGS_SEARCH_*).
@@ -389,7 +392,7 @@ int mgs_graph_destroy(void* graph);
 #define MGS_SEARCH_SOLVED 0         /* h_status values */
 #define MGS_SEARCH_SKIPPED 1        /* doubled 8-bit size below the budget (or no groups) */
 #define MGS_SEARCH_INFEASIBLE 2     /* even the smallest allocation exceeds the budget */
-#define MGS_SEARCH_PRUNED 3         /* LP lower bound above the best optimum: not solved */
+#define MGS_SEARCH_PRUNED 3         /* a lower bound above an attained loss: not solved */
 #define MGS_SEARCH_UNCONVERGED 4    /* calibrated search: max_iter allocations, none within tol */
 
 int mgs_ilp_solve(const double* h_err, const int64_t* h_size, int64_t ncls, int32_t nopt,

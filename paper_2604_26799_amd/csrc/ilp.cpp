@@ -947,6 +947,51 @@ int search_tables(const mgs_sweep_desc* d, const double* h_err, const double* h_
     int spec_rc = MGS_EINVAL;  // the speculative solve: status, loss, size
     double spec_obj = 0;
     int64_t spec_used = 0;
+    // The speculative ratio's LP and greedy incumbent come first: its
+    // multiplier gives every other ratio a bound in one pass over the options
+    // (the Lagrangian bound at a fixed multiplier, below the LP bound), and
+    // a ratio whose bound exceeds the incumbent's loss cannot win or tie (its
+    // optimum is at least that bound, the incumbent's loss at least the best
+    // optimum): it is not solved, and needs no LP bound of its own.
+    Mckp spec_m;
+    int spec_prep = MGS_EINVAL;
+    double lam_spec = 0.0, ub_spec = kInf;
+    if (t_spec >= 0) {
+        const int64_t ncls = (int64_t)C * ((d->h_k[t_spec] + G - 1) / G);
+        spec_m.rebind(filler(t_spec), ncls, nb, budget_bits);
+        spec_prep = spec_m.prepare_bound();
+        if (spec_prep == MGS_OK && !(flags & MGS_SEARCH_ALL)) {  // (every ratio solved: nothing to prune)
+            spec_m.prepare_solve();
+            lam_spec = spec_m.lambda;
+            ub_spec = spec_m.trivial ? spec_m.lower_bound() : spec_m.UB;
+        }
+    }
+    // The one-pass bound of ratio t at multiplier lam: sum over classes of
+    // min_i (loss_i + lam size_i), minus lam times the budget; also the
+    // smallest total size.  False on an invalid option.
+    auto fixed_bound = [&](int t, double lam, double* lbw, double* tolw, int64_t* min_total) {
+        const int64_t ncls = (int64_t)C * ((d->h_k[t] + G - 1) / G);
+        const Mckp::Fill f = filler(t);
+        Opt o[MGS_MAX_BITS];
+        double sum = 0.0, scale = 0.0;
+        int64_t mt = 0;
+        for (int64_t cls = 0; cls < ncls; ++cls) {
+            if (!f(cls, o)) return false;
+            double m = kInf;
+            int64_t smin = o[0].s;
+            for (int i = 0; i < nb; ++i) {
+                m = std::min(m, o[i].e + lam * (double)o[i].s);
+                smin = std::min(smin, o[i].s);
+            }
+            sum += m;
+            scale = std::max(scale, std::fabs(m));
+            mt += smin;
+        }
+        *lbw = sum - lam * (double)budget_bits;
+        *tolw = 1e-9 * (scale + std::fabs(*lbw) + std::fabs(lam * (double)budget_bits)) + 1e-300;
+        *min_total = mt;
+        return true;
+    };
     // per ratio: the checks, the doubled-8-bit test and the LP bound (the
     // speculative ratio is solved exactly as well)
     auto process = [&](int t) {
@@ -989,17 +1034,33 @@ int search_tables(const mgs_sweep_desc* d, const double* h_err, const double* h_
             return;
         }
         if (t == t_spec) {
-            Mckp m(filler(t), ncls, nb, budget_bits);
-            const int rc = m.prepare_bound();
+            const int rc = spec_prep;
             if (rc == MGS_EINFEASIBLE) state[t] = MGS_SEARCH_INFEASIBLE;
             else st[t] = rc;
-            lb[t] = m.lower_bound();
-            lbtol[t] = m.tol;
+            lb[t] = spec_m.lower_bound();
+            lbtol[t] = spec_m.tol;
             if (rc == MGS_OK) {
                 choice[t].resize(ncls);
-                spec_rc = m.exact(choice[t].data(), &spec_obj, &spec_used);
+                spec_rc = spec_m.exact(choice[t].data(), &spec_obj, &spec_used);
             }
             return;
+        }
+        if (ub_spec < kInf) {
+            double lbw = 0.0, tolw = 0.0;
+            int64_t mt = 0;
+            if (!fixed_bound(t, lam_spec, &lbw, &tolw, &mt)) {
+                st[t] = MGS_EINVAL;
+                return;
+            }
+            if (mt > budget_bits) {
+                state[t] = MGS_SEARCH_INFEASIBLE;
+                return;
+            }
+            if (lbw - tolw > ub_spec + 1e-12 * std::fabs(ub_spec)) {
+                state[t] = MGS_SEARCH_PRUNED;
+                lb[t] = lbw;
+                return;
+            }
         }
         static thread_local Mckp wk;
         wk.rebind(filler(t), ncls, nb, budget_bits);
