@@ -184,6 +184,22 @@ def main():
                                                 check=False), s)
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    # The search solves the smallest ratio that passes the doubled-8-bit test
+    # exactly as soon as its tables are on the host and bounds the others as
+    # theirs land: the smallest ratio's tables go first, in copies of their
+    # own, and the rest follow in one copy per table when they are contiguous
+    # (ratio 0 first), else ratio by ratio.  One event per ratio.
+    by_k = sorted(range(len(k)), key=lambda t: (-int(k[t]), t))
+    first = by_k[-1]
+    if first == 0 and len(k) > 1:
+        copy_blocks = [(0, 1), (1, len(k))]
+    else:
+        copy_blocks = [(first, first + 1)] + [(t, t + 1) for t in by_k[:-1]]
+    blk_ev = [torch.cuda.Event() for _ in copy_blocks]
+    tev = [None] * len(k)
+    for (lo, hi), e in zip(copy_blocks, blk_ev):
+        for t in range(lo, hi):
+            tev[t] = e
     stage_ms = {"prune": [], "sweep": [], "d2h": [], "ilp": [], "codes": [], "vq": []}
 
     def step(record: bool):
@@ -197,16 +213,18 @@ def main():
         # stream and runs while the host solves the ILPs
         cs.wait_event(ev[2])
         with torch.cuda.stream(cs):
-            err_h.copy_(tab["err"], non_blocking=True)
-            bits_h.copy_(tab["bits"], non_blocking=True)
+            for (lo, hi), e in zip(copy_blocks, blk_ev):
+                err_h[lo:hi].copy_(tab["err"][lo:hi], non_blocking=True)
+                bits_h[lo:hi].copy_(tab["bits"][lo:hi], non_blocking=True)
+                e.record(cs)
             ev[3].record(cs)
         rc = L.mgs_vq_assign(sh.data_ptr(), args.vq_n, 36, cb.data_ptr(), args.vq_k, idx.data_ptr(), None,
                              nfb.data_ptr(), ws_v.data_ptr(), ws_v.numel(), sp)
         assert rc == 0, mgs.strerror(rc)
         ev[6].record(s)
-        ev[3].synchronize()
+        blk_ev[0].synchronize()  # the host stage is timed from the first tables on the host
         t0 = time.perf_counter()
-        res = mgs.search(w.n, C, k, G, w.bits, err_h.numpy(), bits_h.numpy(), budget_bits)
+        res = mgs.search(w.n, C, k, G, w.bits, err_h.numpy(), bits_h.numpy(), budget_bits, events=tev)
         t1 = time.perf_counter()
         bt = res["best_t"]
         assert bt >= 0, "no admissible reserve ratio"
