@@ -203,6 +203,7 @@ def main():
     stage_ms = {"prune": [], "sweep": [], "d2h": [], "ilp": [], "codes": [], "vq": []}
 
     def step(record: bool):
+        s.wait_event(ev[5])  # the last step's codes have read the kept sets the prune rewrites
         ev[0].record(s)
         mgs.prune_select(imp, k, ws=ws_p, out=kept, stream=s, check=False)
         ev[1].record(s)
@@ -230,19 +231,24 @@ def main():
         assert bt >= 0, "no admissible reserve ratio"
         kt = int(k[bt])
         ng = (kt + G - 1) // G
+        # the final codes on the copy stream: they need the kept sets and the
+        # bit allocation, not the VQ assignment still running on the compute
+        # stream, so the step ends when the later of the two does
         bw_h[:C * ng].copy_(torch.from_numpy(res["best_bits"].reshape(-1)))
-        bw_d[:C * ng].copy_(bw_h[:C * ng], non_blocking=True)
-        ev[4].record(s)
+        with torch.cuda.stream(cs):
+            bw_d[:C * ng].copy_(bw_h[:C * ng], non_blocking=True)
+            ev[4].record(cs)
         kp = kept.data_ptr() + 4 * int(offs[bt])
         rc = L.mgs_quantize(attr.data_ptr(), w.n, C, kp, kt, G, bw_d.data_ptr(), codes.data_ptr(),
-                            gmn.data_ptr(), gmx.data_ptr(), sp)
+                            gmn.data_ptr(), gmx.data_ptr(), cs.cuda_stream)
         assert rc == 0, mgs.strerror(rc)
         rc = L.mgs_dequantize(codes.data_ptr(), kt, C, G, bw_d.data_ptr(), gmn.data_ptr(), gmx.data_ptr(),
-                              recon.data_ptr(), sp)
+                              recon.data_ptr(), cs.cuda_stream)
         assert rc == 0, mgs.strerror(rc)
-        ev[5].record(s)
+        ev[5].record(cs)
         if record:
             s.synchronize()
+            cs.synchronize()
             stage_ms["prune"].append(ev[0].elapsed_time(ev[1]))
             stage_ms["sweep"].append(ev[1].elapsed_time(ev[2]))
             stage_ms["d2h"].append(ev[2].elapsed_time(ev[3]))
