@@ -263,7 +263,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(True)
+        bt_last = step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print(f"timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
@@ -272,6 +272,21 @@ def main():
         rc = mgs.status(ws, stream=s)
         assert rc == 0, mgs.strerror(rc)
     graph.close()
+    # the last step's final codes once more, alone on the GPU (in the steps
+    # they run beside the VQ assignment): the kernels' own durations
+    kt_last = int(k[bt_last])
+    ea = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ea[0].record(s)
+    rc = L.mgs_quantize(attr.data_ptr(), w.n, C, kept.data_ptr() + 4 * int(offs[bt_last]), kt_last, G,
+                        bw_d.data_ptr(), codes.data_ptr(), gmn.data_ptr(), gmx.data_ptr(), sp)
+    assert rc == 0, mgs.strerror(rc)
+    ea[1].record(s)
+    rc = L.mgs_dequantize(codes.data_ptr(), kt_last, C, G, bw_d.data_ptr(), gmn.data_ptr(), gmx.data_ptr(),
+                          recon.data_ptr(), sp)
+    assert rc == 0, mgs.strerror(rc)
+    ea[2].record(s)
+    ea[2].synchronize()
+    codes_alone = {"quantize_ms": ea[0].elapsed_time(ea[1]), "dequantize_ms": ea[1].elapsed_time(ea[2])}
 
     ms_step = elapsed * 1e3 / args.steps
     med = {key: float(np.median(v)) for key, v in stage_ms.items()}
@@ -298,6 +313,7 @@ def main():
                                f"VQ {args.vq_n}x36, K={args.vq_k}",
                    "evals_per_step": evals, "sweep_shape": tuned},
         "stages_ms_median": med,
+        "codes_alone_ms": codes_alone,
         "sweep_kernel": {
             "avg_launch_ms": sweep_avg_s * 1e3,
             "evals_per_s": evals / sweep_avg_s,

@@ -17,7 +17,6 @@
 namespace mgs {
 namespace {
 
-constexpr int QU = 8;  // dequantizer: elements per thread and batch (independent loads in flight)
 
 __device__ __forceinline__ int clamp_bits(uint8_t b) { return b < 1 ? 1 : (b > 16 ? 16 : b); }
 
@@ -119,22 +118,32 @@ __global__ __launch_bounds__(QT) void quantize_kernel(const float* __restrict__ 
     }
 }
 
-template <int QT>
-__global__ __launch_bounds__(QT) void dequantize_kernel(const uint16_t* __restrict__ codes,
-                                                        int64_t k, int C, int G, int64_t ng,
+// Dequantizer: a workgroup takes one piece of DT * 8 codes of a group (so
+// that a launch has many more workgroups than CUs even for few groups), and
+// each thread 8 consecutive codes: one 16-byte load and two 16-byte stores
+// when the piece starts on a multiple of 8 elements of the row and the
+// buffers are 16-byte aligned (vec), element by element otherwise.
+constexpr int DQ_PER = 8;
+template <int DT>
+__global__ __launch_bounds__(DT) void dequantize_kernel(const uint16_t* __restrict__ codes,
+                                                        int64_t k, int C, int G, int64_t ng, int nchunk,
                                                         const uint8_t* __restrict__ bw,
                                                         const float* __restrict__ gmin,
                                                         const float* __restrict__ gmax,
-                                                        float* __restrict__ out) {
-    constexpr int CAP = QT * QU;
+                                                        float* __restrict__ out, int vec) {
     const int tid = threadIdx.x;
-    for (int64_t blk = blockIdx.x; blk < (int64_t)C * ng; blk += gridDim.x) {
-        const int c = (int)(blk / ng);
-        const int64_t g = blk - (int64_t)c * ng;
-        const int64_t j0 = g * G;
-        const int n = (int)std::min<int64_t>(G, k - j0);
-        const float mn = gmin[blk], mx = gmax[blk];
-        const int b = clamp_bits(bw[blk]);
+    const int64_t nblk = (int64_t)C * ng * nchunk;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t grp = blk / nchunk;  // (channel, group), channel-major
+        const int ch = (int)(blk - grp * nchunk);
+        const int c = (int)(grp / ng);
+        const int64_t g = grp - (int64_t)c * ng;
+        const int64_t j0 = g * G + (int64_t)ch * DT * DQ_PER;
+        const int64_t gend = std::min<int64_t>(k, (g + 1) * (int64_t)G);
+        if (j0 >= gend) continue;
+        const int m = (int)std::min<int64_t>(DT * DQ_PER, gend - j0);
+        const float mn = gmin[grp], mx = gmax[grp];
+        const int b = clamp_bits(bw[grp]);
         const float P = ldexpf(1.0f, b);
         const float R = mx - mn;
         const float S = R / P;
@@ -143,26 +152,33 @@ __global__ __launch_bounds__(QT) void dequantize_kernel(const uint16_t* __restri
             float r = mx / S;
             Z = __builtin_rintf(P - r);
         }
-        const uint16_t* q = codes + (int64_t)c * k + j0;
-        float* o = out + (int64_t)c * k + j0;
-        for (int b0 = 0; b0 < n; b0 += CAP) {
-            uint16_t qv[QU];
-#pragma unroll
-            for (int u = 0; u < QU; ++u) {
-                const int j = b0 + u * QT + tid;
-                qv[u] = j < n ? q[j] : (uint16_t)0;
+        auto deq = [&](uint32_t q) {
+            float v = mn;
+            if (S != 0.0f) {
+                float d = (float)q - Z;
+                v = d * S;
             }
+            return v;
+        };
+        const int64_t off = (int64_t)c * k + j0;
+        const int e0 = tid * DQ_PER;
+        if (vec && (off % DQ_PER) == 0 && e0 + DQ_PER <= m) {
+            const uint4 raw = *reinterpret_cast<const uint4*>(codes + off + e0);
+            const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+            float v[DQ_PER];
 #pragma unroll
-            for (int u = 0; u < QU; ++u) {
-                const int j = b0 + u * QT + tid;
-                if (j < n) {
-                    float v = mn;
-                    if (S != 0.0f) {
-                        float d = (float)qv[u] - Z;
-                        v = d * S;
-                    }
-                    o[j] = v;
-                }
+            for (int i = 0; i < 4; ++i) {
+                v[2 * i] = deq(w[i] & 0xFFFFu);
+                v[2 * i + 1] = deq(w[i] >> 16);
+            }
+            float4* o4 = reinterpret_cast<float4*>(out + off + e0);
+            o4[0] = make_float4(v[0], v[1], v[2], v[3]);
+            o4[1] = make_float4(v[4], v[5], v[6], v[7]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < DQ_PER; ++i) {
+                const int e = e0 + i;
+                if (e < m) out[off + e] = deq(codes[off + e]);
             }
         }
     }
@@ -203,12 +219,11 @@ extern "C" int mgs_dequantize(const uint16_t* d_codes, int64_t k, int32_t C, int
     if (k == 0) return MGS_OK;
     if (!d_codes || !d_bw || !d_gmin || !d_gmax || !d_out) return MGS_EINVAL;
     const int64_t ng = (k + G - 1) / G;
-    const int64_t blocks = std::min<int64_t>((int64_t)C * ng, 1 << 20);
-    if (G >= 4096)
-        hipLaunchKernelGGL(mgs::dequantize_kernel<1024>, dim3((unsigned)blocks), dim3(1024), 0,
-                           (hipStream_t)stream, d_codes, k, C, G, ng, d_bw, d_gmin, d_gmax, d_out);
-    else
-        hipLaunchKernelGGL(mgs::dequantize_kernel<256>, dim3((unsigned)blocks), dim3(256), 0,
-                           (hipStream_t)stream, d_codes, k, C, G, ng, d_bw, d_gmin, d_gmax, d_out);
+    constexpr int DT = 256;
+    const int nchunk = (G + DT * mgs::DQ_PER - 1) / (DT * mgs::DQ_PER);
+    const int64_t blocks = std::min<int64_t>((int64_t)C * ng * nchunk, 1 << 20);
+    const int vec = ((uintptr_t)d_codes % 16 == 0) && ((uintptr_t)d_out % 16 == 0);
+    hipLaunchKernelGGL(mgs::dequantize_kernel<DT>, dim3((unsigned)blocks), dim3(DT), 0, (hipStream_t)stream,
+                       d_codes, k, C, G, ng, nchunk, d_bw, d_gmin, d_gmax, d_out, vec);
     return mgs_last_launch();
 }
