@@ -9,7 +9,7 @@
 // smaller key (-0 and +0 map alike).  The kept set of count k is exactly
 // {i : ck(i) <= thr}, thr being the k-th smallest key, so ties need no
 // special treatment.  thr is found per k by a radix select over six digits
-// (11/11/10 bits of the importance key, then 11/11/10 bits of the index):
+// (13/11/8 bits of the importance key, then 11/11/10 bits of the index):
 // one histogram pass over the importance per digit, each followed by a tiny
 // per-k kernel that picks the digit holding the k-th key.  Passes after the
 // first only count keys that still match a k's prefix, found through an LDS
@@ -29,13 +29,15 @@ namespace mgs {
 namespace {
 
 constexpr int PR_LEVELS = 6;
-constexpr int PR_BINS = 2048;
+constexpr int PR_BINS = 8192;  // bins of the widest digit
 constexpr int PR_HIST_THREADS = 256;
 constexpr int PR_CHUNK_THREADS = 256;
 constexpr int PR_CHUNK_ROUNDS = 16;
 constexpr int PR_CHUNK = PR_CHUNK_THREADS * PR_CHUNK_ROUNDS;  // elements per compaction block
-constexpr int PR_SHIFT[PR_LEVELS] = {53, 42, 32, 21, 10, 0};
-constexpr int PR_BITS[PR_LEVELS] = {11, 11, 10, 11, 11, 10};
+// a wide first digit, so that few keys share a k's prefix in the second pass
+// (those are counted with global atomics)
+constexpr int PR_SHIFT[PR_LEVELS] = {51, 40, 32, 21, 10, 0};
+constexpr int PR_BITS[PR_LEVELS] = {13, 11, 8, 11, 11, 10};
 
 struct PruneState {
     uint64_t prefix;  // key bits fixed so far (above the current digit)
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(PR_HIST_THREADS) void prune_hist0_kernel(PruneArgs 
          i += (int64_t)gridDim.x * PR_HIST_THREADS) {
         float v = a.imp[i];
         bad |= (uint32_t)!finite_f32(v);
-        atomicAdd(&h[desc_key(v) >> 21], 1u);
+        atomicAdd(&h[desc_key(v) >> (32 - PR_BITS[0])], 1u);
     }
     if (bad) atomicOr(&a.status->nonfinite, 1u);
     __syncthreads();
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(256) void prune_select_kernel(PruneArgs a, int leve
     __shared__ uint32_t found_digit, found_count;
     const uint32_t* h = level_hist(a, level, t);
     const int nbins = 1 << PR_BITS[level];
-    const int per = PR_BINS / 256;  // 8 bins per thread (only the first nbins used)
+    const int per = PR_BINS / 256;  // 32 bins per thread (only the first nbins used)
     const int b0 = threadIdx.x * per;
     uint32_t mine = 0;
     for (int j = 0; j < per; ++j)
