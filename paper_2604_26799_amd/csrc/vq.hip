@@ -26,14 +26,15 @@
 //      s~_j <= min s~ + 2 E_i; a small FP64 slack 2 delta_i also admits the
 //      winner of the FP64 definition when exact distances tie within FP64
 //      rounding.
-//   3. One pass over the codebook.  Each lane keeps its running minimum m of
-//      the scores it has seen and records the tiles whose smallest score is
-//      within T_i of it, with a mask of their codewords scoring at most
-//      m + T_i (m taken after the tile; up to 8 tiles per lane).  A tile that
-//      lowers m so far that m + T_i falls below the previous minimum clears
-//      the list: every earlier tile scored at least that previous minimum, so
-//      above the final threshold (the row minimum only falls), and cannot
-//      hold the winner.  Thresholds only fall, so each mask holds every
+//   3. One pass over the codebook.  Both lanes of a row keep the row's
+//      running minimum m of the scores seen so far and record the tiles whose
+//      smallest score (over the row's 32 codewords of the tile) is within T_i
+//      of it; each lane stores a mask of its own codewords scoring at most
+//      m + T_i (m taken after the tile; up to 8 tiles per lane, none when the
+//      mask is empty).  A tile that lowers m so far that m + T_i falls below
+//      the previous minimum clears the lists: every earlier recorded tile
+//      scored at least that previous minimum, so above the final threshold
+//      (the row minimum only falls), and cannot hold the winner.  Thresholds only fall, so each mask holds every
 //      codeword under the final threshold.  The row's candidates are then
 //      re-scored with the FP64 definition (same operation order) and the
 //      smallest (distance, index) wins.  Rows with more candidate tiles than
@@ -347,7 +348,16 @@ void vq_main_kernel(VqArgs a) {
                 float tmin = sc[0];
 #pragma unroll
                 for (int i = 1; i < 16; ++i) tmin = fminf(tmin, sc[i]);
-                if (!(tmin <= mrun[rs] + T[rs])) continue;  // most lane-tiles hold no candidate
+                // the row's smallest score in the tile: lanes l and l ^ 32 hold
+                // its two halves (v_permlane32_swap exchanges the halves), so
+                // both lanes of a row keep the same running minimum and decide
+                // alike (half as many independent decisions per wavefront)
+                {
+                    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(tmin), __float_as_uint(tmin),
+                                                                     false, false);
+                    tmin = fminf(tmin, fminf(__uint_as_float(sw[0]), __uint_as_float(sw[1])));
+                }
+                if (!(tmin <= mrun[rs] + T[rs])) continue;  // most row-tiles hold no candidate
                 const float mo = mrun[rs];
                 mrun[rs] = fminf(mo, tmin);
                 const float thr = mrun[rs] + T[rs];
@@ -360,6 +370,7 @@ void vq_main_kernel(VqArgs a) {
                 for (int i = 0; i < 16; ++i)
                     neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(thr - sc[i]), 31);
                 const uint32_t bits = ~neg & 0xFFFFu;
+                if (bits == 0u) continue;  // this lane's half of the tile holds none
                 if (cnt[rs] < VQ_CAND) {
                     cand_t[wave][rs][cnt[rs]][lane] = jbase;
                     cand_m[wave][rs][cnt[rs]][lane] = (uint16_t)bits;
