@@ -34,11 +34,13 @@
 //      mask is empty).  A tile that lowers m so far that m + T_i falls below
 //      the previous minimum clears the lists: every earlier recorded tile
 //      scored at least that previous minimum, so above the final threshold
-//      (the row minimum only falls), and cannot hold the winner.  Thresholds only fall, so each mask holds every
-//      codeword under the final threshold.  The row's candidates are then
-//      re-scored with the FP64 definition (same operation order) and the
-//      smallest (distance, index) wins.  Rows with more candidate tiles than
-//      slots go to an exact FP64 full scan.
+//      (the row minimum only falls), and cannot hold the winner.  Thresholds
+//      only fall, so each mask holds every codeword under the final
+//      threshold.  The row's candidates are then re-scored, two at a time,
+//      with the FP64 definition (same operation order) and the smallest
+//      (distance, index) wins.  Rows with more candidate tiles than slots go
+//      to an exact FP64 full scan.  Padding codewords (up to whole chunks)
+//      score +inf and never become candidates.
 // The result equals the FP64 definition bit for bit.
 //
 // Layout.  The prepared codebook is stored chunk by chunk (64 codewords) as
@@ -79,6 +81,7 @@ struct VqArgs {
     int64_t N;
     int32_t D, K, Kpad, KP;
     int32_t xvec;         // D % 4 == 0 and x 16-byte aligned: rows load as float4
+    int32_t cvec;         // D % 4 == 0 and the codebook 16-byte aligned: codewords load as float4
 };
 
 // The scale of the MFMA operands: 2^(6 - e) for cmax in [2^e, 2^(e+1)), so
@@ -125,10 +128,12 @@ __global__ __launch_bounds__(256) void vq_norm_kernel(VqArgs a) {
 }
 
 // Prepared codebook: -2 sigma c and the high and low FP16 parts of
-// ||sigma c||^2 (FP64), zero padding; padding codewords (j >= K) are all
-// zero and masked in the main kernel.  One thread per codeword; the loops
-// run over the compile-time row width, so the codeword's loads are all issued
-// before use and its row is written as 16-byte units.
+// ||sigma c||^2 (FP64), zero padding.  Padding codewords (j >= K) are zero
+// but for an infinite norm part: against the constant 1 of every X row they
+// score +inf (the other products are 0 x finite), so they never lower a
+// minimum nor pass a threshold.  One thread per codeword; the loops run over
+// the compile-time row width, so the codeword's loads are all issued before
+// use and its row is written as 16-byte units.
 template <int KS>
 __global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
     constexpr int KP = 16 * KS;
@@ -138,7 +143,13 @@ __global__ __launch_bounds__(256) void vq_prep_kernel(VqArgs a) {
     f16x8* row = (f16x8*)(a.cbp + (int64_t)(j / VQ_CHUNK) * VQ_CHUNK * KP) + (j % VQ_CHUNK);
     if (j >= a.K) {
 #pragma unroll
-        for (int u = 0; u < KP / 8; ++u) row[u * VQ_CHUNK] = f16x8{};
+        for (int u = 0; u < KP / 8; ++u) {
+            f16x8 w{};
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (8 * u + i == a.D) w[i] = (_Float16)INFINITY;
+            row[u * VQ_CHUNK] = w;
+        }
         return;
     }
     const float sg = vq_scale(__uint_as_float(*a.cmax_bits));
@@ -172,6 +183,47 @@ __device__ __forceinline__ double exact_dist(const float* __restrict__ x, const 
         s += d * d;
     }
     return s;
+}
+
+// The distances of one row to two codewords, each the same terms added in
+// the same order as above, from float4 loads: the row and both codewords are
+// read in batches of four float4 groups, a batch's loads all issued before its
+// first use (a group past D is read from the row's last group and ignored),
+// and the two sums are independent chains.  Needs D % 4 == 0 and 16-byte
+// aligned rows.
+template <int NG>
+__device__ __forceinline__ void exact_dist_vec2(const float* __restrict__ x, const float* __restrict__ c0,
+                                                const float* __restrict__ c1, int D, double* d0, double* d1) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int g0 = 0; g0 < NG; g0 += 4) {
+        if (4 * g0 >= D) break;
+        float4 xv[4], av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k0 = 4 * (g0 + i) < D ? 4 * (g0 + i) : D - 4;
+            xv[i] = *(const float4*)(x + k0);
+            av[i] = *(const float4*)(c0 + k0);
+            bv[i] = *(const float4*)(c1 + k0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float xe[4] = {xv[i].x, xv[i].y, xv[i].z, xv[i].w};
+            const float ae[4] = {av[i].x, av[i].y, av[i].z, av[i].w};
+            const float be[4] = {bv[i].x, bv[i].y, bv[i].z, bv[i].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * (g0 + i) + e < D) {
+                    const double xd = (double)xe[e];
+                    const double da = xd - (double)ae[e];
+                    const double db = xd - (double)be[e];
+                    s0 += da * da;
+                    s1 += db * db;
+                }
+        }
+    }
+    *d0 = s0;
+    *d1 = s1;
 }
 
 template <int KS>
@@ -232,15 +284,15 @@ void vq_main_kernel(VqArgs a) {
                     const float4 q = t[ks][i >> 2];
                     const float e = (i & 3) == 0 ? q.x : (i & 3) == 1 ? q.y : (i & 3) == 2 ? q.z : q.w;
                     float v = 0.0f;
-                    if (r < a.N) {
-                        if (k < D) {
+                    if (k < D) {
+                        if (r < a.N) {
                             bad |= (uint32_t)!finite_f32(e);
                             n2 += e * e;
                             v = e * sg;
                             bg |= !(fabsf(v) < 32768.0f);
-                        } else if (k == D || k == D + 1) {
-                            v = 1.0f;
                         }
+                    } else if (k == D || k == D + 1) {
+                        v = 1.0f;  // every row, rows past N too (a padding codeword then scores +inf)
                     }
                     breg[rs][ks][i] = (_Float16)v;
                 }
@@ -251,16 +303,16 @@ void vq_main_kernel(VqArgs a) {
                 for (int i = 0; i < 8; ++i) {
                     const int k = 16 * ks + 8 * half + i;
                     float v = 0.0f;
-                    if (r < a.N) {
-                        if (k < D) {
+                    if (k < D) {
+                        if (r < a.N) {
                             const float e = a.x[r * D + k];
                             bad |= (uint32_t)!finite_f32(e);
                             n2 += e * e;
                             v = e * sg;
                             bg |= !(fabsf(v) < 32768.0f);
-                        } else if (k == D || k == D + 1) {
-                            v = 1.0f;
                         }
+                    } else if (k == D || k == D + 1) {
+                        v = 1.0f;
                     }
                     breg[rs][ks][i] = (_Float16)v;
                 }
@@ -337,14 +389,9 @@ void vq_main_kernel(VqArgs a) {
             const int jbase = c0 + tile * 32;
 #pragma unroll
             for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
-                float sc[16];
+                float sc[16];  // padding codewords score +inf
 #pragma unroll
                 for (int i = 0; i < 16; ++i) sc[i] = acc[rs][i];
-                if (jbase + 32 > K) {  // the codebook's last tile: padding codewords never count
-#pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        if (jbase + 8 * (i >> 2) + 4 * half + (i & 3) >= K) sc[i] = INFINITY;
-                }
                 float tmin = sc[0];
 #pragma unroll
                 for (int i = 1; i < 16; ++i) tmin = fminf(tmin, sc[i]);
@@ -425,21 +472,51 @@ void vq_main_kernel(VqArgs a) {
         int32_t bj = 0x7fffffff;
         if (r < a.N && !ovf_row) {
             const float* xr = a.x + r * D;
-            for (int e = 0; e < cnt[rs]; ++e) {
-                const int jbase = cand_t[wave][rs][e][lane];
-                uint32_t bits = cand_m[wave][rs][e][lane];
-                while (bits) {
-                    const int i = 15 - __builtin_ctz(bits);  // bit 15 - i holds element i
-                    bits &= bits - 1;
-                    // output element i of this lane: codeword row 8*(i/4) + 4*half + i%4
-                    const int32_t j = jbase + 8 * (i >> 2) + 4 * half + (i & 3);
-                    if (j >= K) continue;
-                    const double d = exact_dist(xr, a.cb + (int64_t)j * D, D);
-                    if (d < best || (d == best && j < bj)) {
-                        best = d;
-                        bj = j;
+            const bool vec = a.xvec && a.cvec;  // float4 rows and codewords
+            int e = 0;
+            int jbase = cnt[rs] > 0 ? cand_t[wave][rs][0][lane] : 0;
+            uint32_t bits = cnt[rs] > 0 ? cand_m[wave][rs][0][lane] : 0u;
+            // the lane's next candidate codeword; false once none is left
+            auto next = [&](int32_t& j) {
+                for (;;) {
+                    while (bits) {
+                        const int i = 15 - __builtin_ctz(bits);  // bit 15 - i holds element i
+                        bits &= bits - 1;
+                        // output element i of this lane: codeword row 8*(i/4) + 4*half + i%4
+                        j = jbase + 8 * (i >> 2) + 4 * half + (i & 3);
+                        if (j < K) return true;
                     }
+                    if (++e >= cnt[rs]) return false;
+                    jbase = cand_t[wave][rs][e][lane];
+                    bits = cand_m[wave][rs][e][lane];
                 }
+            };
+            auto take = [&](int32_t j, double d) {
+                if (d < best || (d == best && j < bj)) {
+                    best = d;
+                    bj = j;
+                }
+            };
+            // candidates in pairs (an odd last one is scored twice)
+            int32_t j0 = 0, j1 = 0;
+            bool more = next(j0);
+            while (more) {
+                if (!next(j1)) {
+                    j1 = j0;
+                    more = false;
+                }
+                const float* c0 = a.cb + (int64_t)j0 * D;
+                const float* c1 = a.cb + (int64_t)j1 * D;
+                double d0, d1;
+                if (vec) {
+                    exact_dist_vec2<KP / 4>(xr, c0, c1, D, &d0, &d1);
+                } else {
+                    d0 = exact_dist(xr, c0, D);
+                    d1 = exact_dist(xr, c1, D);
+                }
+                take(j0, d0);
+                take(j1, d1);
+                if (more) more = next(j0);
             }
         }
         const double ob = __shfl_xor(best, 32, MGS_WAVE);
@@ -516,7 +593,7 @@ VqLayout vq_layout(int64_t N, int D, int K) {
     VqLayout L;
     L.KS = (D + 2 + 15) / 16;
     L.KP = 16 * L.KS;
-    // whole chunks: padding codewords are masked in the main kernel
+    // whole chunks: padding codewords score +inf in the main kernel
     L.Kpad = (int)(((int64_t)K + VQ_CHUNK - 1) / VQ_CHUNK * VQ_CHUNK);
     size_t o = MGS_STATUS_BYTES;
     L.cmax = o;
@@ -566,6 +643,7 @@ extern "C" int mgs_vq_assign(const float* d_x, int64_t N, int32_t D, const float
     a.Kpad = L.Kpad;
     a.KP = L.KP;
     a.xvec = (D % 4 == 0) && ((uintptr_t)d_x % 16 == 0);
+    a.cvec = (D % 4 == 0) && ((uintptr_t)d_cb % 16 == 0);
     int rc = mgs_fill<uint32_t>((uint32_t*)ws, 64, 0u, s);       // status word
     if (rc) return rc;
     rc = mgs_fill<uint32_t>(a.cmax_bits, 64, 0u, s);              // norm maximum + fallback count
