@@ -500,6 +500,24 @@ def test_vq_duplicates_and_self(torch, orc):
     assert (host(idx)[400:450] == np.arange(50)).all()
 
 
+@pytest.mark.parametrize("K,D", [(33, 36), (70, 36), (1, 8), (100, 5)])
+def test_vq_zero_rows_against_padding(torch, orc, K, D):
+    """Rows of zeros score ||sigma c_j||^2 >= 0 against every real codeword;
+    the codebook is padded to whole 64-codeword chunks, and a padding codeword
+    that scored 0 would set the running minimum below every real score and
+    hide the winner.  Zero rows, rows of one codeword and random rows, with a
+    row count that leaves the last workgroup partly empty."""
+    rng = np.random.default_rng(41 + K)
+    cb = (rng.laplace(0, 0.3, (K, D)) + np.float32(0.5)).astype(np.float32)
+    x = rng.laplace(0, 0.3, (777, D)).astype(np.float32)
+    x[::3] = 0.0
+    x[1::5] = cb[rng.integers(0, K, x[1::5].shape[0])]
+    idx, dist, _ = mgs.vq_assign(dev(torch, x), dev(torch, cb))
+    want_i, want_d = orc.vq_assign(x, cb)
+    np.testing.assert_array_equal(host(idx), want_i)
+    np.testing.assert_array_equal(host(dist), want_d)
+
+
 @pytest.mark.parametrize("case", ["x_far_larger", "x_far_smaller", "huge_codebook"])
 def test_vq_operand_ranges(torch, orc, case):
     """The MFMA operands are sigma x and sigma c in FP16 with sigma set by the
