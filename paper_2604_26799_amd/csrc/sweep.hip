@@ -444,18 +444,47 @@ void sweep_kernel(SweepParams p) {
         // stay fixed during this one: read through the constant address
         // space, so that their uniform fields come in through scalar loads.
         const constant_ptr<SceneDesc> sc = (constant_ptr<SceneDesc>)(p.scenes + sid);
-        int t, c0, g;
+        int t, c0, c1, g;
         {
             const int64_t lt = it - p.tcum[sid];
             const int64_t gpc = sc->gpc;
-            const int cc = (int)(lt / gpc);
-            const int r = ((constant_ptr<int32_t>)sc->order)[(int)(lt - (int64_t)cc * gpc)];
-            c0 = cc * p.cpb;
+            int64_t rank;
+            if (p.tsplit) {
+                // One scene, all channels per tile, persistent grid: XCD x's
+                // counter range holds the groups [x gpx, (x+1) gpx) of the
+                // tile order, the first ones whole and the last tranks of them
+                // in tparts channel runs of tcpb channels each, so that the
+                // range ends in small tiles and the workgroups finish close
+                // together.  Indices past the range's real tiles (a last range
+                // with fewer groups) hold no tile.
+                const int x = (int)(lt / p.tper);
+                const int64_t local = lt - (int64_t)x * p.tper;
+                const int64_t r0 = (int64_t)x * p.tgpx;
+                const int64_t nrx = max((int64_t)0, min((int64_t)p.tgpx, gpc - r0));
+                const int64_t sx = min((int64_t)p.tranks, nrx);
+                const int64_t whole = nrx - sx;
+                if (local < whole) {
+                    rank = r0 + local;
+                    c0 = 0;
+                    c1 = sc->C;
+                } else {
+                    const int64_t j = local - whole;
+                    if (j >= sx * p.tparts) continue;
+                    rank = r0 + whole + j / p.tparts;
+                    c0 = (int)(j % p.tparts) * p.tcpb;
+                    c1 = min(sc->C, c0 + p.tcpb);
+                }
+            } else {
+                const int cc = (int)(lt / gpc);
+                rank = lt - (int64_t)cc * gpc;
+                c0 = cc * p.cpb;
+                c1 = min(sc->C, c0 + p.cpb);
+            }
+            const int r = ((constant_ptr<int32_t>)sc->order)[(int)rank];
             t = 0;
             while (t + 1 < sc->T && sc->gcum[t + 1] <= r) ++t;
             g = r - sc->gcum[t];
         }
-        const int c1 = min(sc->C, c0 + p.cpb);
         const int64_t j0 = (int64_t)g * sc->G;
         const int64_t krem = sc->k[t] - j0;
         const int n = (int)(krem < sc->G ? krem : sc->G);
@@ -1348,6 +1377,11 @@ extern "C" size_t mgs_quant_sweep_multi_ws_bytes(const mgs_sweep_job* h_jobs, in
     return sweep_ws_bytes(njobs, h_jobs[0].desc.G, groups);
 }
 
+// Split tail of a persistent launch: groups cut at the end of each XCD's
+// range, and about how many channel runs each.
+static constexpr int64_t kTailRanks = 32;
+static constexpr int kTailParts = 5;
+
 // One launch over the tiles of `n` scenes that share G and the bit list.
 static int sweep_launch_scenes(mgs::SceneDesc* scs, int n, void* d_ws, size_t ws_bytes,
                                hipStream_t s, const mgs::Shape* force) {
@@ -1389,6 +1423,28 @@ static int sweep_launch_scenes(mgs::SceneDesc* scs, int n, void* d_ws, size_t ws
     for (int i = 0; i < n; ++i)
         p.tcum[i + 1] = p.tcum[i] + (int64_t)((scs[i].C + p.cpb - 1) / p.cpb) * scs[i].gpc;
     p.ntiles = p.tcum[n];
+    // A persistent launch of one scene with all channels per tile ends each
+    // XCD's range of groups with the last kTailRanks groups cut into channel
+    // runs (about kTailParts of them): whole-group tiles are long, and the
+    // workgroups that take the last ones would otherwise finish up to one
+    // such tile after the others.
+    p.tsplit = 0;
+    if (n == 1 && sh.persist && p.cpb >= scs[0].C && scs[0].C >= 2 && scs[0].gpc > 0) {
+        const int C = scs[0].C;
+        const int tcpb = (C + kTailParts - 1) / kTailParts;
+        const int parts = (C + tcpb - 1) / tcpb;
+        if (parts >= 2) {
+            const int64_t gpx = ((int64_t)scs[0].gpc + MGS_XCDS - 1) / MGS_XCDS;
+            const int64_t ranks = std::min<int64_t>(gpx, kTailRanks);
+            p.tsplit = 1;
+            p.tcpb = tcpb;
+            p.tparts = parts;
+            p.tgpx = gpx;
+            p.tranks = ranks;
+            p.tper = (gpx - ranks) + ranks * parts;
+            p.ntiles = p.tcum[1] = p.tper * MGS_XCDS;
+        }
+    }
     auto* status = (mgs_status_block*)d_ws;
     auto* d_sc = (SceneDesc*)((char*)d_ws + sweep_ws_scene_off());
     auto* lgtab = (double*)((char*)d_ws + sweep_ws_table_off(n));
