@@ -249,6 +249,26 @@ void vq_main_kernel(VqArgs a) {
     const int D = a.D, K = a.K;
     const int64_t row0 = (int64_t)blockIdx.x * VQ_ROWS + wave * (VQ_ROWSETS * 32);
 
+    // Asynchronous copy of chunk c0 of the prepared codebook into buffer
+    // `dst`: wave w moves units [(i*VQ_WAVES + w)*64, +64) of the chunk; the
+    // LDS base of each instruction is uniform over the wave.
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    auto prefetch = [&](int c0, _Float16* dst) {
+        constexpr int nunits = VQ_CHUNK * UNITS;  // Kpad is a whole number of chunks
+        const char* src = (const char*)(a.cbp + (int64_t)c0 * KP);
+#pragma unroll
+        for (int i = 0; i < (VQ_CHUNK * UNITS + VQ_THREADS - 1) / VQ_THREADS; ++i) {
+            const int ublk = (i * VQ_WAVES + wave_u) * MGS_WAVE;
+            if (ublk + lane < nunits)
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(src + (size_t)(ublk + lane) * 16),
+                    (__attribute__((address_space(3))) void*)((char*)dst + ublk * 16), 16, 0, 0);
+        }
+    };
+    // the first chunk's copy is under way while the rows are read and the
+    // bounds computed
+    prefetch(0, cbs0);
+
     // ---- B operands (the scaled X rows), bound T per row
     f16x8 breg[VQ_ROWSETS][KS];
     float T[VQ_ROWSETS];
@@ -342,22 +362,6 @@ void vq_main_kernel(VqArgs a) {
         cnt[rs] = 0;
     }
 
-    // Asynchronous copy of chunk c0 of the prepared codebook into buffer
-    // `dst`: wave w moves units [(i*VQ_WAVES + w)*64, +64) of the chunk; the
-    // LDS base of each instruction is uniform over the wave.
-    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-    auto prefetch = [&](int c0, _Float16* dst) {
-        constexpr int nunits = VQ_CHUNK * UNITS;  // Kpad is a whole number of chunks
-        const char* src = (const char*)(a.cbp + (int64_t)c0 * KP);
-#pragma unroll
-        for (int i = 0; i < (VQ_CHUNK * UNITS + VQ_THREADS - 1) / VQ_THREADS; ++i) {
-            const int ublk = (i * VQ_WAVES + wave_u) * MGS_WAVE;
-            if (ublk + lane < nunits)
-                __builtin_amdgcn_global_load_lds(
-                    (const void*)(src + (size_t)(ublk + lane) * 16),
-                    (__attribute__((address_space(3))) void*)((char*)dst + ublk * 16), 16, 0, 0);
-        }
-    };
     const int nchunks = a.Kpad / VQ_CHUNK;
     // Chunk step q reads buffer q % 2 while the next chunk is copied into the
     // other one.
@@ -451,7 +455,6 @@ void vq_main_kernel(VqArgs a) {
         __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next chunk has landed
         __syncthreads();                // ... and everyone's; this buffer is free
     };
-    prefetch(0, cbs0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // step q reads buffer q % 2
