@@ -257,6 +257,29 @@ def test_sweep_every_shape_identical(torch, orc):
         mgs.sweep_set_shape(16384, len(bits), max(bits), 0, 0, 0, 0)
 
 
+def test_sweep_split_tail(torch, orc):
+    """A persistent launch of one scene with whole-group tiles ends each XCD's
+    range of groups in tiles of a few channels.  323 groups of 256 (the last
+    one ragged) over 11 channels: every range holds whole and split groups,
+    and the last range has fewer groups than the others.  The tables match
+    the oracle and, bit for bit, the same sweep in one-channel tiles."""
+    G, bits = 256, [2, 5, 9]
+    k = np.array([323 * G - 100], np.int64)
+    attr, imp = synth.scene(int(k[0]) + 7000, 11, seed=12)
+    kept = orc.prune_select(imp, k)
+    want = orc.quant_sweep(attr, imp, kept, k, G, bits)
+    try:
+        mgs.sweep_set_shape(G, len(bits), max(bits), 256, 1, 0, 0, 1)
+        got = gpu_sweep(torch, attr, imp, kept, k, G, bits, hist=False)
+        assert_tables(got, want, hist=False, G=G)
+        mgs.sweep_set_shape(G, len(bits), max(bits), 256, 1, 0, 1, 0)
+        plain = gpu_sweep(torch, attr, imp, kept, k, G, bits, hist=False)
+        for key in ("err", "bits", "gmin", "gmax"):
+            assert np.array_equal(got[key], plain[key], equal_nan=True), key
+    finally:
+        mgs.sweep_set_shape(G, len(bits), max(bits), 0, 0, 0, 0)
+
+
 @pytest.mark.parametrize("scale", [1e-38, 1e38])
 def test_sweep_extreme_weights(torch, orc, scale):
     """Importance weights at the ends of the FP32 range: the FP32 loss terms
