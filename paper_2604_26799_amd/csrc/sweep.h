@@ -68,9 +68,10 @@ struct SweepParams {
     int32_t nbatches, nentries, max_batch_words;
     int32_t kgrid;            // K of the increment grid
     int32_t persist;          // persistent grid: tiles from the per-XCD counters of status->queue
-    // split tail (one scene, all channels per tile, persistent): each XCD's
-    // range of tper tile indices covers tgpx groups of the tile order, the
-    // last tranks of them as tparts runs of tcpb channels
+    // split tail (all channels per tile, persistent): each XCD's range of
+    // tper tile indices covers tgpx groups of the scenes' tile orders in
+    // sequence, the last tranks of them as tparts runs of tcpb channels; tcum
+    // then holds the prefix of the scenes' groups
     int32_t tsplit, tcpb, tparts;
     int64_t tgpx, tranks, tper;
     int32_t batch_begin[MGS_MAX_ENTRIES + 1];

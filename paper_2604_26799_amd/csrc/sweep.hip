@@ -439,44 +439,52 @@ void sweep_kernel(SweepParams p) {
         // with the run's groups taken in the scene's tile order; channels
         // [c0, c1)
         int sid = 0;
-        while (sid + 1 < p.nscenes && p.tcum[sid + 1] <= it) ++sid;
+        int64_t rank;
+        int part = -1;  // split tail: the channel run of a split group (-1: the whole group)
+        int cc = 0;     // plain tiles: the channel run
+        if (p.tsplit) {
+            // All channels per tile, persistent grid: the scenes' groups in one
+            // sequence (scene by scene, each in its tile order; tcum holds the
+            // prefix of the groups).  XCD x's counter range holds the groups
+            // [x gpx, (x+1) gpx) of it, the first ones whole and the last
+            // tranks of them in tparts channel runs of tcpb channels each, so
+            // that the range ends in small tiles and the workgroups finish
+            // close together.  Indices past the range's real tiles (a last
+            // range with fewer groups) hold no tile.
+            const int x = (int)(it / p.tper);
+            const int64_t local = it - (int64_t)x * p.tper;
+            const int64_t r0 = (int64_t)x * p.tgpx;
+            const int64_t nrx = max((int64_t)0, min((int64_t)p.tgpx, p.tcum[p.nscenes] - r0));
+            const int64_t sx = min((int64_t)p.tranks, nrx);
+            const int64_t whole = nrx - sx;
+            int64_t grank;
+            if (local < whole) {
+                grank = r0 + local;
+            } else {
+                const int64_t j = local - whole;
+                if (j >= sx * p.tparts) continue;
+                grank = r0 + whole + j / p.tparts;
+                part = (int)(j % p.tparts);
+            }
+            while (sid + 1 < p.nscenes && p.tcum[sid + 1] <= grank) ++sid;
+            rank = grank - p.tcum[sid];
+        } else {
+            while (sid + 1 < p.nscenes && p.tcum[sid + 1] <= it) ++sid;
+            const int64_t lt = it - p.tcum[sid];
+            const int64_t gpc = ((constant_ptr<SceneDesc>)(p.scenes + sid))->gpc;
+            cc = (int)(lt / gpc);
+            rank = lt - (int64_t)cc * gpc;
+        }
         // The descriptors and tile orders were written by the init kernel and
         // stay fixed during this one: read through the constant address
         // space, so that their uniform fields come in through scalar loads.
         const constant_ptr<SceneDesc> sc = (constant_ptr<SceneDesc>)(p.scenes + sid);
         int t, c0, c1, g;
         {
-            const int64_t lt = it - p.tcum[sid];
-            const int64_t gpc = sc->gpc;
-            int64_t rank;
             if (p.tsplit) {
-                // One scene, all channels per tile, persistent grid: XCD x's
-                // counter range holds the groups [x gpx, (x+1) gpx) of the
-                // tile order, the first ones whole and the last tranks of them
-                // in tparts channel runs of tcpb channels each, so that the
-                // range ends in small tiles and the workgroups finish close
-                // together.  Indices past the range's real tiles (a last range
-                // with fewer groups) hold no tile.
-                const int x = (int)(lt / p.tper);
-                const int64_t local = lt - (int64_t)x * p.tper;
-                const int64_t r0 = (int64_t)x * p.tgpx;
-                const int64_t nrx = max((int64_t)0, min((int64_t)p.tgpx, gpc - r0));
-                const int64_t sx = min((int64_t)p.tranks, nrx);
-                const int64_t whole = nrx - sx;
-                if (local < whole) {
-                    rank = r0 + local;
-                    c0 = 0;
-                    c1 = sc->C;
-                } else {
-                    const int64_t j = local - whole;
-                    if (j >= sx * p.tparts) continue;
-                    rank = r0 + whole + j / p.tparts;
-                    c0 = (int)(j % p.tparts) * p.tcpb;
-                    c1 = min(sc->C, c0 + p.tcpb);
-                }
+                c0 = part < 0 ? 0 : part * p.tcpb;
+                c1 = part < 0 ? sc->C : min(sc->C, c0 + p.tcpb);
             } else {
-                const int cc = (int)(lt / gpc);
-                rank = lt - (int64_t)cc * gpc;
                 c0 = cc * p.cpb;
                 c1 = min(sc->C, c0 + p.cpb);
             }
@@ -1423,18 +1431,20 @@ static int sweep_launch_scenes(mgs::SceneDesc* scs, int n, void* d_ws, size_t ws
     for (int i = 0; i < n; ++i)
         p.tcum[i + 1] = p.tcum[i] + (int64_t)((scs[i].C + p.cpb - 1) / p.cpb) * scs[i].gpc;
     p.ntiles = p.tcum[n];
-    // A persistent launch of one scene with all channels per tile ends each
-    // XCD's range of groups with the last kTailRanks groups cut into channel
-    // runs (about kTailParts of them): whole-group tiles are long, and the
-    // workgroups that take the last ones would otherwise finish up to one
-    // such tile after the others.
+    // A persistent launch with all channels per tile (scenes with equal
+    // channel counts) ends each XCD's range of groups with the last
+    // kTailRanks groups cut into channel runs (about kTailParts of them):
+    // whole-group tiles are long, and the workgroups that take the last ones
+    // would otherwise finish up to one such tile after the others.
     p.tsplit = 0;
-    if (n == 1 && sh.persist && p.cpb >= scs[0].C && scs[0].C >= 2 && scs[0].gpc > 0) {
-        const int C = scs[0].C;
+    bool same_c = true;
+    for (int i = 1; i < n; ++i) same_c = same_c && scs[i].C == s0.C;
+    if (sh.persist && same_c && p.cpb >= s0.C && s0.C >= 2 && groups > 0) {
+        const int C = s0.C;
         const int tcpb = (C + kTailParts - 1) / kTailParts;
         const int parts = (C + tcpb - 1) / tcpb;
         if (parts >= 2) {
-            const int64_t gpx = ((int64_t)scs[0].gpc + MGS_XCDS - 1) / MGS_XCDS;
+            const int64_t gpx = (groups + MGS_XCDS - 1) / MGS_XCDS;
             const int64_t ranks = std::min<int64_t>(gpx, kTailRanks);
             p.tsplit = 1;
             p.tcpb = tcpb;
@@ -1442,7 +1452,8 @@ static int sweep_launch_scenes(mgs::SceneDesc* scs, int n, void* d_ws, size_t ws
             p.tgpx = gpx;
             p.tranks = ranks;
             p.tper = (gpx - ranks) + ranks * parts;
-            p.ntiles = p.tcum[1] = p.tper * MGS_XCDS;
+            for (int i = 0; i < n; ++i) p.tcum[i + 1] = p.tcum[i] + scs[i].gpc;  // (groups, not tiles)
+            p.ntiles = p.tper * MGS_XCDS;
         }
     }
     auto* status = (mgs_status_block*)d_ws;

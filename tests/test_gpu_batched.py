@@ -58,6 +58,38 @@ def test_multi_scene_equals_single_and_oracle(torch, orc):
         np.testing.assert_allclose(out["bits"].cpu().numpy()[~nan], want["bits"][~nan], rtol=1e-9, atol=1e-6)
 
 
+def test_multi_scene_split_tail(torch, orc):
+    """A persistent launch with all channels per tile takes the scenes'
+    groups in sequence and ends each XCD's range of them in tiles of a few
+    channels (355 groups of 256: whole and split groups in every range,
+    ranges across scene boundaries, a shorter last range).  Every scene's
+    tables equal those of the same launch in one-channel tiles, bit for bit,
+    and the oracle's."""
+    g, bits = 256, [2, 5, 9]
+    scenes = [scene(torch, orc, 40000, 6, [0.3, 0.9], 21), scene(torch, orc, 25000, 6, [0.5, 1.0], 22),
+              scene(torch, orc, 7000, 6, [0.7], 23)]
+    try:
+        mgs.sweep_set_shape(g, len(bits), max(bits), 256, 1, 0, 0, 1)
+        outs = mgs.quant_sweep_multi(scenes, g, bits)
+        torch.cuda.synchronize()
+        mgs.sweep_set_shape(g, len(bits), max(bits), 256, 1, 0, 1, 0)
+        plain = mgs.quant_sweep_multi(scenes, g, bits)
+        torch.cuda.synchronize()
+    finally:
+        mgs.sweep_set_shape(g, len(bits), max(bits), 0, 0, 0, 0)
+    for sc, out, pl in zip(scenes, outs, plain):
+        assert same(out, pl)
+        attr, imp, kept = sc["host"]
+        want = orc.quant_sweep(attr, imp, kept, sc["k"], g, bits)
+        nan = np.isnan(want["err"])
+        err = out["err"].cpu().numpy()
+        assert np.array_equal(np.isnan(err), nan)
+        np.testing.assert_allclose(err[~nan], want["err"][~nan], rtol=4e-6)
+        np.testing.assert_allclose(out["bits"].cpu().numpy()[~nan], want["bits"][~nan], rtol=1e-9, atol=1e-6)
+        assert np.array_equal(out["gmin"].cpu().numpy()[~np.isnan(want["gmin"])],
+                              want["gmin"][~np.isnan(want["gmin"])])
+
+
 def test_multi_scene_histograms(torch, orc):
     scenes = [scene(torch, orc, 9000, 4, [0.5, 1.0], 5), scene(torch, orc, 6000, 2, [0.3], 6)]
     bits = [1, 3, 7]
