@@ -354,11 +354,13 @@ void vq_main_kernel(VqArgs a) {
     }
     if (bad) atomicOr(&a.status->nonfinite, 1u);
 
-    float mrun[VQ_ROWSETS];  // running minimum of the lane's scores
+    float mrun[VQ_ROWSETS];  // running minimum of the row's scores
+    float mthr[VQ_ROWSETS];  // mrun + T, the recording threshold
     int cnt[VQ_ROWSETS];
 #pragma unroll
     for (int rs = 0; rs < VQ_ROWSETS; ++rs) {
         mrun[rs] = INFINITY;
+        mthr[rs] = mrun[rs] + T[rs];
         cnt[rs] = 0;
     }
 
@@ -408,10 +410,11 @@ void vq_main_kernel(VqArgs a) {
                                                                      false, false);
                     tmin = fminf(tmin, fminf(__uint_as_float(sw[0]), __uint_as_float(sw[1])));
                 }
-                if (!(tmin <= mrun[rs] + T[rs])) continue;  // most row-tiles hold no candidate
+                if (!(tmin <= mthr[rs])) continue;  // most row-tiles hold no candidate
                 const float mo = mrun[rs];
                 mrun[rs] = fminf(mo, tmin);
                 const float thr = mrun[rs] + T[rs];
+                mthr[rs] = thr;
                 if (thr < mo) cnt[rs] = 0;  // no earlier tile can hold the winner
                 // sign bits of thr - s, shifted in by v_alignbit (element i
                 // lands in bit 15 - i); s <= thr  <=>  thr - s >= 0 (an exact
