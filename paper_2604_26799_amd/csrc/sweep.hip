@@ -905,30 +905,38 @@ __global__ void scene_copy_kernel(SceneDesc sd, SceneDesc* dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = sd;
 }
 
-// Position of group g of ratio t along the Gaussian index: the middle of its
-// run of kept positions as a fraction of k_t.  Kept indices ascend, so groups
-// of different ratios at similar positions read nearby Gaussians.
-__device__ __forceinline__ double group_pos(const SceneDesc* sc, int t, int g) {
-    const int64_t j0 = (int64_t)g * sc->G;
-    const int64_t n = min((int64_t)sc->G, sc->k[t] - j0);
-    return (double)(2 * j0 + n) / (double)(2 * sc->k[t]);
+// Position of group g of a ratio with k kept Gaussians along the Gaussian
+// index: the middle of its run of kept positions as a fraction of k,
+// (2 g G + n) times inv = 1 / (2 k) (every position is computed the same
+// way, so the positions of one ratio increase with g and all of them are
+// ordered consistently).  Kept indices ascend, so groups of different ratios
+// at similar positions read nearby Gaussians.
+__device__ __forceinline__ double group_pos(int64_t k, int G, int g, double inv) {
+    const int64_t j0 = (int64_t)g * G;
+    const int64_t n = min((int64_t)G, k - j0);
+    return (double)(2 * j0 + n) * inv;
 }
 
 // Tile order of a channel run: its groups sorted by (position, ratio).  The
 // rank of group (t, g) counts, per ratio, the groups before it (positions
-// increase with g, so a binary search per ratio); order[rank] = r.
-__device__ void tile_order(SceneDesc* sc, int r) {
+// increase with g, so a binary search per ratio); order[rank] = r.  The keep
+// counts and group prefixes come from LDS copies (sk, sg): the searches are
+// chains of dependent reads.
+__device__ void tile_order(const SceneDesc* sc, const int64_t* sk, const int32_t* sg, int r) {
+    const int T = sc->T, G = sc->G;
     int t = 0;
-    while (t + 1 < sc->T && sc->gcum[t + 1] <= r) ++t;
-    const int g = r - sc->gcum[t];
-    const double pos = group_pos(sc, t, g);
+    while (t + 1 < T && sg[t + 1] <= r) ++t;
+    const int g = r - sg[t];
+    const double pos = group_pos(sk[t], G, g, 1.0 / (double)(2 * sk[t]));
     int rank = g;
-    for (int u = 0; u < sc->T; ++u) {
+    for (int u = 0; u < T; ++u) {
         if (u == t) continue;
-        int lo = 0, hi = sc->gcum[u + 1] - sc->gcum[u];
+        const int64_t ku = sk[u];
+        const double inv = 1.0 / (double)(2 * ku);
+        int lo = 0, hi = sg[u + 1] - sg[u];
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            const double pm = group_pos(sc, u, mid);
+            const double pm = group_pos(ku, G, mid, inv);
             if (pm < pos || (pm == pos && u < t)) lo = mid + 1;
             else hi = mid;
         }
@@ -956,10 +964,20 @@ __global__ void sweep_init_kernel(SceneDesc* __restrict__ scenes, int count,
         lgtab[h] = t0;
         inc[h] = grid_round(t1, K) - grid_round(t0, K);
     }
+    __shared__ int64_t sk[MGS_MAX_RATIOS];
+    __shared__ int32_t sg[MGS_MAX_RATIOS + 1];
     for (int s = 0; s < count; ++s) {
         SceneDesc* sc = &scenes[s];
-        for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < sc->gpc; r += gridDim.x * blockDim.x)
-            tile_order(sc, r);
+        if ((int64_t)blockIdx.x * blockDim.x < sc->gpc) {  // (block-uniform) this block orders groups
+            __syncthreads();  // the previous scene's searches are done with sk, sg
+            for (int u = threadIdx.x; u <= sc->T; u += blockDim.x) {
+                if (u < sc->T) sk[u] = sc->k[u];
+                sg[u] = sc->gcum[u];
+            }
+            __syncthreads();
+            for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < sc->gpc; r += gridDim.x * blockDim.x)
+                tile_order(sc, sk, sg, r);
+        }
         const int64_t nslot = (int64_t)sc->T * sc->C * sc->gmaxn;
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslot;
              i += (int64_t)gridDim.x * blockDim.x) {
